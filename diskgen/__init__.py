@@ -1,0 +1,353 @@
+"""Seeded synthetic inputs for the thin-disk force: densities, slopes, AMR layouts.
+
+This module is shared by the oracle tests and the GPU path's tests and
+benchmark.  It produces inputs only (surface densities, their first-order
+slopes, composite AMR layouts, batches and request streams); it holds none of
+the force computation.  Every random draw comes from
+``numpy.random.default_rng(seed)``.
+
+Layout conventions: arrays are row-major [y, x] (row j = y index, x fastest).
+A uniform grid of n x n cells covers [x0, x0 + n h] x [y0, y0 + n h]; the
+default is [-1, 1]^2.  Slopes (dsx, dsy) are the first-order Taylor
+coefficients of Section 2 of the paper: the exact gradient at the cell centre
+for analytic profiles, second-order central differences (one-sided at the
+domain edge) for sampled noisy ones.
+"""
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# uniform grids and analytic profiles
+# ----------------------------------------------------------------------------
+
+
+def grid_centres(n, x0=-1.0, y0=-1.0, h=None):
+    """Cell-centre coordinates (X, Y), each (n, n), of an n x n grid."""
+    if h is None:
+        h = 2.0 / n
+    c = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(x0 + c, y0 + c)
+    return X, Y
+
+
+def kuzmin(X, Y, M=1.0, a=0.2, centre=(0.0, 0.0)):
+    """Kuzmin disk s = M a / (2 pi (r^2 + a^2)^{3/2}) and its exact gradient."""
+    dx = X - centre[0]
+    dy = Y - centre[1]
+    q = dx * dx + dy * dy + a * a
+    s = M * a / (2 * np.pi * q ** 1.5)
+    g = -3.0 * s / q
+    return s, g * dx, g * dy
+
+
+def d2(X, Y, alpha=0.25, sigma0=1.0, centre=(0.0, 0.0)):
+    """D2 disk s0 (1 - R^2/alpha^2)^{3/2} (zero outside) and its exact gradient."""
+    dx = X - centre[0]
+    dy = Y - centre[1]
+    t = np.clip(1.0 - (dx * dx + dy * dy) / alpha ** 2, 0.0, None)
+    s = sigma0 * t ** 1.5
+    g = -3.0 * sigma0 * np.sqrt(t) / alpha ** 2
+    return s, g * dx, g * dy
+
+
+def d22(X, Y, alpha=0.25, sigma0=1.0):
+    """Two D2 disks centred at (0, 0.5) and (0, -0.5)."""
+    a = d2(X, Y, alpha, sigma0, (0.0, 0.5))
+    b = d2(X, Y, alpha, sigma0, (0.0, -0.5))
+    return a[0] + b[0], a[1] + b[1], a[2] + b[2]
+
+
+def spiral(X, Y, base="exp", scale=0.25, amp=0.1, pitch_deg=20.0, phase=0.0):
+    """base(r) (1 + amp cos(2 theta - ln r / tan(pitch) + phase)) and exact gradient.
+
+    base = "exp": exp(-r/scale); base = "kuzmin": (1 + r^2/scale^2)^{-3/2}.
+    """
+    r = np.hypot(X, Y)
+    th = np.arctan2(Y, X)
+    tp = np.tan(np.deg2rad(pitch_deg))
+    if base == "exp":
+        b = np.exp(-r / scale)
+        db = -b / scale
+    elif base == "kuzmin":
+        q = 1.0 + (r / scale) ** 2
+        b = q ** -1.5
+        db = -3.0 * r / scale ** 2 * q ** -2.5
+    else:
+        raise ValueError(base)
+    ph = 2 * th - np.log(r) / tp + phase
+    f = 1.0 + amp * np.cos(ph)
+    s = b * f
+    ds_dr = db * f + b * amp * np.sin(ph) / (r * tp)
+    ds_dth = -2.0 * amp * b * np.sin(ph)
+    dsx = ds_dr * X / r - ds_dth * Y / (r * r)
+    dsy = ds_dr * Y / r + ds_dth * X / (r * r)
+    return s, dsx, dsy
+
+
+def central_slopes(s, h):
+    """Second-order differences of sampled s: central inside, one-sided at edges."""
+    s = np.asarray(s, dtype=np.float64)
+    return np.gradient(s, h, axis=1, edge_order=2), np.gradient(s, h, axis=0, edge_order=2)
+
+
+def noisy_spiral(n, seed, noise=0.01):
+    """Exponential spiral disk exp(-r/0.25)(1 + 0.1 cos(2 theta - ln r / tan 20deg))
+    times (1 + noise xi), xi ~ N(0,1) per cell, clamped at 0; slopes by
+    central differences.  Returns (sigma, dsx, dsy, h)."""
+    X, Y = grid_centres(n)
+    h = 2.0 / n
+    s, _, _ = spiral(X, Y, "exp", 0.25, 0.1, 20.0, 0.0)
+    rng = np.random.default_rng(seed)
+    s = np.clip(s * (1.0 + noise * rng.standard_normal(s.shape)), 0.0, None)
+    dsx, dsy = central_slopes(s, h)
+    return s, dsx, dsy, h
+
+
+def random_fields(n, seed, slopes=True):
+    """Seeded random (sigma, dsx, dsy) on n x n (for property tests)."""
+    rng = np.random.default_rng(seed)
+    s = rng.random((n, n))
+    if not slopes:
+        return s, None, None
+    return s, rng.standard_normal((n, n)), rng.standard_normal((n, n))
+
+
+# ----------------------------------------------------------------------------
+# composite AMR layouts
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class Patch:
+    """A rectangle of cells at refinement level ``level`` >= 1 (base = 0),
+    with lower-left cell (i0, j0) in that level's global cell index."""
+    level: int
+    i0: int
+    j0: int
+    nx: int
+    ny: int
+
+
+@dataclass
+class Block:
+    level: int
+    i0: int
+    j0: int
+    nx: int
+    ny: int
+    x0: float      # lower-left corner of the block
+    y0: float
+    h: float
+    offset: int    # start of this block in the composite-packed arrays
+    leaf_mask: np.ndarray = field(repr=False)  # (ny, nx) bool
+
+
+@dataclass
+class Layout:
+    """Base n0 x n0 grid on [x0, x0 + n0 h0]^2 plus properly nested patches.
+
+    Composite-packed arrays hold the base block first, then each patch in
+    list order, each row-major [y, x]; covered (non-leaf) cells are present
+    but ignored on input and zero on output.
+    """
+    n0: int
+    nlevels: int
+    patches: List[Patch]
+    x0: float = -1.0
+    y0: float = -1.0
+    h0: float = None
+
+    def __post_init__(self):
+        if self.h0 is None:
+            self.h0 = 2.0 / self.n0
+
+    def h(self, level):
+        return self.h0 / 2 ** level
+
+    @property
+    def n_finest(self):
+        return self.n0 * 2 ** (self.nlevels - 1)
+
+    def total(self):
+        return self.n0 * self.n0 + sum(p.nx * p.ny for p in self.patches)
+
+    def blocks(self):
+        """Blocks in composite-packed order with their leaf masks."""
+        out = []
+        rects = [Patch(0, 0, 0, self.n0, self.n0)] + list(self.patches)
+        off = 0
+        for b in rects:
+            h = self.h(b.level)
+            mask = np.ones((b.ny, b.nx), dtype=bool)
+            for c in self.patches:
+                if c.level != b.level + 1:
+                    continue
+                # child footprint in this level's index (ratio 2)
+                ci0, cj0 = c.i0 // 2, c.j0 // 2
+                ci1, cj1 = (c.i0 + c.nx + 1) // 2, (c.j0 + c.ny + 1) // 2
+                a0, a1 = max(ci0, b.i0), min(ci1, b.i0 + b.nx)
+                c0, c1 = max(cj0, b.j0), min(cj1, b.j0 + b.ny)
+                if a0 < a1 and c0 < c1:
+                    mask[c0 - b.j0:c1 - b.j0, a0 - b.i0:a1 - b.i0] = False
+            out.append(Block(b.level, b.i0, b.j0, b.nx, b.ny, self.x0 + b.i0 * h,
+                             self.y0 + b.j0 * h, h, off, mask))
+            off += b.nx * b.ny
+        return out
+
+    def nleaves(self):
+        return int(sum(b.leaf_mask.sum() for b in self.blocks()))
+
+    def leaf_mask(self):
+        """Composite-packed boolean mask of leaf cells."""
+        return np.concatenate([b.leaf_mask.ravel() for b in self.blocks()])
+
+    def centres(self):
+        """Composite-packed cell-centre coordinates (x, y), all cells."""
+        xs, ys = [], []
+        for b in self.blocks():
+            X = b.x0 + (np.arange(b.nx) + 0.5) * b.h
+            Y = b.y0 + (np.arange(b.ny) + 0.5) * b.h
+            XX, YY = np.meshgrid(X, Y)
+            xs.append(XX.ravel())
+            ys.append(YY.ravel())
+        return np.concatenate(xs), np.concatenate(ys)
+
+    def areas(self):
+        return np.concatenate([np.full(b.nx * b.ny, b.h * b.h) for b in self.blocks()])
+
+    def sample(self, profile):
+        """Evaluate profile(X, Y) -> (s, dsx, dsy) at every cell centre; covered
+        cells are zeroed.  Returns composite-packed float64 arrays."""
+        X, Y = self.centres()
+        s, dx, dy = profile(X, Y)
+        m = self.leaf_mask()
+        return (np.where(m, s, 0.0), np.where(m, dx, 0.0), np.where(m, dy, 0.0))
+
+    def validate(self):
+        """Proper nesting: each level-l patch lies inside the union of level-(l-1)
+        blocks, and same-level patches are disjoint."""
+        for p in self.patches:
+            if not (1 <= p.level < self.nlevels):
+                return False
+            n = self.n0 * 2 ** p.level
+            if p.i0 < 0 or p.j0 < 0 or p.i0 + p.nx > n or p.j0 + p.ny > n:
+                return False
+            if p.i0 % 2 or p.j0 % 2 or p.nx % 2 or p.ny % 2:
+                return False
+        for l in range(1, self.nlevels):
+            n = self.n0 * 2 ** l
+            occ = np.zeros((n, n), dtype=np.int32)
+            for p in self.patches:
+                if p.level == l:
+                    occ[p.j0:p.j0 + p.ny, p.i0:p.i0 + p.nx] += 1
+            if occ.max(initial=0) > 1:
+                return False
+            if l >= 2:
+                par = np.zeros((n // 2, n // 2), dtype=bool)
+                for p in self.patches:
+                    if p.level == l - 1:
+                        par[p.j0:p.j0 + p.ny, p.i0:p.i0 + p.nx] = True
+                for p in self.patches:
+                    if p.level == l and not par[p.j0 // 2:(p.j0 + p.ny) // 2,
+                                                p.i0 // 2:(p.i0 + p.nx) // 2].all():
+                        return False
+        return True
+
+
+def flag_layout(profile, n0, nlevels, tile=16, thresh=0.1, x0=-1.0, y0=-1.0, h0=None):
+    """Refine tiles of tile x tile parent cells into (2 tile)^2 child patches
+    wherever max over the tile of h_parent |grad s| / s exceeds ``thresh``;
+    level l+1 tiles are only taken inside level-l patches (proper nesting)."""
+    if h0 is None:
+        h0 = 2.0 / n0
+    patches = []
+    parents = [Patch(0, 0, 0, n0, n0)]
+    for lvl in range(1, nlevels):
+        hp = h0 / 2 ** (lvl - 1)
+        new = []
+        for par in parents:
+            for tj in range(par.j0, par.j0 + par.ny, tile):
+                for ti in range(par.i0, par.i0 + par.nx, tile):
+                    c = (np.arange(tile) + 0.5) * hp
+                    X, Y = np.meshgrid(x0 + ti * hp + c, y0 + tj * hp + c)
+                    s, dx, dy = profile(X, Y)
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        score = np.where(s > 0, hp * np.hypot(dx, dy) / s, 0.0)
+                    if np.max(score) > thresh:
+                        new.append(Patch(lvl, 2 * ti, 2 * tj, 2 * tile, 2 * tile))
+        patches.extend(new)
+        parents = new
+        if not new:
+            break
+    return Layout(n0, nlevels, patches, x0, y0, h0)
+
+
+def clumps(seed, n=8, rmax=0.7):
+    """Seeded Gaussian clumps A exp(-|x - xk|^2 / (2 w^2)): A ~ U[1,10],
+    w ~ U[0.01, 0.04], centres uniform in the disk r < rmax."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(1, 10, n)
+    w = rng.uniform(0.01, 0.04, n)
+    r = rmax * np.sqrt(rng.random(n))
+    t = rng.uniform(0, 2 * np.pi, n)
+    return A, w, r * np.cos(t), r * np.sin(t)
+
+
+def kuzmin_clumps_profile(seed, a=0.02, nclumps=8):
+    """Kuzmin disk (M = 1, scale a) plus seeded Gaussian clumps, exact gradient."""
+    A, w, cx, cy = clumps(seed, nclumps)
+
+    def prof(X, Y):
+        s, dx, dy = kuzmin(X, Y, 1.0, a)
+        for k in range(len(A)):
+            e = A[k] * np.exp(-((X - cx[k]) ** 2 + (Y - cy[k]) ** 2) / (2 * w[k] ** 2))
+            s = s + e
+            dx = dx - e * (X - cx[k]) / w[k] ** 2
+            dy = dy - e * (Y - cy[k]) / w[k] ** 2
+        return s, dx, dy
+
+    return prof
+
+
+def amr_config(seed, n0=256, nlevels=3, thresh=0.1, a=0.02):
+    """3-level AMR workload: base n0^2 on [-1,1]^2, 32x32 child patches flagged
+    by h |grad s| / s > thresh, Kuzmin (a) plus clumps, exact slopes."""
+    prof = kuzmin_clumps_profile(seed, a)
+    lay = flag_layout(prof, n0, nlevels, 16, thresh)
+    s, dx, dy = lay.sample(prof)
+    return lay, s, dx, dy
+
+
+def table10_layout():
+    """The paper's Appendix A example: 4 x 4 base on [0,1]^2; base cells 6 and
+    11 (1-based, row-major) refined to level 2; level-2 cells 17 and 19
+    (x in [0.25,0.375] y in [0.375,0.5], and x in [0.375,0.5] y in [0.25,0.375])
+    refined to level 3.  28 leaves (14 / 6 / 8)."""
+    patches = [Patch(1, 2, 2, 2, 2), Patch(1, 4, 4, 2, 2),
+               Patch(2, 4, 6, 2, 2), Patch(2, 6, 4, 2, 2)]
+    return Layout(4, 3, patches, 0.0, 0.0, 0.25)
+
+
+# ----------------------------------------------------------------------------
+# batches and request streams
+# ----------------------------------------------------------------------------
+
+
+def batch_disks(seed, count=64, sizes=(64, 128, 256, 512, 1024)):
+    """Independent uniform disks: n ~ U(sizes), profile exponential or
+    Kuzmin-like (p = 1/2), scale ~ U[0.05, 0.5], m = 2 amplitude ~ U[0, 0.2],
+    phase ~ U[0, 2 pi), exact slopes.  Returns a list of (n, s, dsx, dsy)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(sizes))
+        base = "exp" if rng.random() < 0.5 else "kuzmin"
+        scale = rng.uniform(0.05, 0.5)
+        amp = rng.uniform(0.0, 0.2)
+        ph = rng.uniform(0, 2 * np.pi)
+        X, Y = grid_centres(n)
+        s, dx, dy = spiral(X, Y, base, scale, amp, 20.0, ph)
+        out.append((n, s, dx, dy))
+    return out
