@@ -1,0 +1,178 @@
+/*
+ * gravity.h -- C ABI of the MI355X thin-disk self-gravity library.
+ *
+ * The library computes the midplane force (F_x, F_y) of an infinitesimally
+ * thin disk whose surface density is given, on disjoint rectangular zones, by
+ * a first-order Taylor polynomial s_i + dsx_i (x - x_i) + dsy_i (y - y_i)
+ * (Tseng, Shang & Yen, Section 2, the decomposition over zones D_i and the
+ * Taylor density of each zone).  The force at every zone centre is
+ *
+ *   F_x = G sum_i [ s_i K^{x,0}_i + dsx_i K^{x,x}_i + dsy_i K^{x,y}_i ]
+ *
+ * (and F_y likewise) with the exact cell-integrated kernels of Section 2 at
+ * z = 0.  On a uniform grid this double sum is a discrete convolution
+ * (Section 4, the FFT form of the uniform-grid sum) and is evaluated by
+ * zero-padded 2D FFTs, free of artificial boundary conditions.  On an AMR
+ * grid (Section 3, Berger-Oliger refinement with leaf zones only) the same
+ * leaf-by-leaf sum is evaluated exactly by injecting every leaf's linear
+ * density onto the finest lattice and convolving with cell-centre kernels
+ * (targets that are finest leaves) and lattice-corner kernels (targets that
+ * are coarser leaves, whose centres are finest-lattice corners).
+ *
+ * Conventions
+ *  - All array arguments of gravity_solve / gravity_solve_batch are DEVICE
+ *    pointers owned by the caller; they must stay valid until the work queued
+ *    on `stream` has completed.  `stream` is a hipStream_t (NULL = the null
+ *    stream).  Calls return once the work is queued.
+ *  - Element type of every array is float for GRAVITY_F32 plans and double
+ *    for GRAVITY_F64 plans.
+ *  - "Composite packed" layout: the base n0 x n0 block first, then each patch
+ *    of the descriptor in order; each block row-major (row = y index, x
+ *    fastest).  Cells covered by a finer patch are not leaves: their input
+ *    values are ignored and their outputs are written as 0.  A uniform grid
+ *    is the base block alone.
+ *  - Errors are returned as status codes; nothing aborts or throws across the
+ *    ABI.  gravity_last_error() gives a message for the calling thread's last
+ *    non-OK status.  A device fault surfaces as GRAVITY_EDEVICE.
+ *
+ * Thread safety: plans are immutable after creation; concurrent solves on
+ * one plan are safe when each uses its own workspace and outputs.
+ */
+#ifndef GRAVITY_H
+#define GRAVITY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gravity_plan_s *gravity_plan_t;
+
+typedef enum {
+    GRAVITY_OK = 0,
+    GRAVITY_EINVAL = 1,       /* malformed descriptor or arguments */
+    GRAVITY_ENOMEM = 2,       /* device allocation failed */
+    GRAVITY_EDEVICE = 3,      /* HIP runtime or kernel error */
+    GRAVITY_EUNSUPPORTED = 4, /* valid request outside the supported sizes */
+    GRAVITY_EBUSY = 5         /* resource temporarily unavailable */
+} gravity_status_t;
+
+typedef enum { GRAVITY_F32 = 0, GRAVITY_F64 = 1 } gravity_prec_t;
+
+/* GRAVITY_SLOPES_GIVEN: the first-order Taylor slopes (dsx, dsy) of every
+ * zone are inputs (the paper's second-order method).  GRAVITY_SLOPES_NONE:
+ * piecewise-constant density, dsx = dsy = 0 (first order). */
+typedef enum { GRAVITY_SLOPES_NONE = 0, GRAVITY_SLOPES_GIVEN = 1 } gravity_slopes_t;
+
+/* A rectangle of nx x ny cells at refinement level `level` (1 .. nlevels-1;
+ * the base grid is level 0; refinement ratio 2), lower-left cell (i0, j0) in
+ * that level's global cell index.  i0, j0, nx, ny must be even, patches of
+ * one level disjoint, and each patch must lie inside the level below it. */
+typedef struct {
+    int32_t level, i0, j0, nx, ny;
+} gravity_patch_t;
+
+typedef struct {
+    int32_t n0x, n0y;               /* base cells per side; equal, power of two */
+    double x0, y0;                  /* lower-left corner of the domain */
+    double h0;                      /* base cell size */
+    int32_t nlevels;                /* 1 = uniform grid */
+    int32_t npatches;
+    const gravity_patch_t *patches; /* host array, copied at plan time */
+    gravity_prec_t prec;
+    gravity_slopes_t slopes;
+    double G;                       /* gravitational constant */
+} gravity_desc_t;
+
+typedef struct {
+    int32_t n_finest;    /* finest lattice cells per side, n0 * 2^(nlevels-1) */
+    int32_t fft_size;    /* zero-padded FFT size per side, 2 * n_finest */
+    int64_t n_cells;     /* composite-packed array length (all cells) */
+    int64_t n_leaves;    /* leaf zones (forces computed) */
+    size_t workspace_bytes;
+    size_t resident_bytes; /* device memory held by the plan and its spectra */
+} gravity_plan_info_t;
+
+/*
+ * Create a plan: validates the descriptor and builds (or takes from the
+ * resident cache) the kernel spectra for its FFT size and precision.  The
+ * kernel tables are the exact integrals of Section 2 (K^{x,0}, K^{x,x},
+ * K^{x,y} and the y family) at every source offset, built in double
+ * precision on the device and transformed with a double precision FFT.
+ * Sizes: 16 <= n_finest <= 4096, powers of two.
+ * Errors: EINVAL (bad descriptor or nesting), EUNSUPPORTED (size or
+ * non-square grid), ENOMEM, EDEVICE.  *out is NULL on error.
+ * Runs on the calling thread's current HIP device, which the plan records;
+ * solves must be issued with that device current.
+ */
+gravity_status_t gravity_plan(const gravity_desc_t *desc, gravity_plan_t *out);
+
+/* Bytes of device workspace one gravity_solve on this plan needs. */
+gravity_status_t gravity_plan_workspace_bytes(gravity_plan_t plan, size_t *bytes);
+
+/* Sizes of a plan (see gravity_plan_info_t). */
+gravity_status_t gravity_plan_get_info(gravity_plan_t plan, gravity_plan_info_t *info);
+
+/*
+ * Queue one solve on `stream`.
+ *   sigma, dsx, dsy : composite-packed inputs (dsx, dsy may be NULL only for
+ *                     GRAVITY_SLOPES_NONE plans; they are ignored there)
+ *   fx, fy          : composite-packed outputs (leaf forces, 0 elsewhere)
+ *   workspace       : device buffer of gravity_plan_workspace_bytes bytes,
+ *                     256-byte aligned, not shared with concurrent solves
+ * Errors: EINVAL (NULL pointer, misaligned workspace), EDEVICE.
+ */
+gravity_status_t gravity_solve(gravity_plan_t plan, const void *sigma, const void *dsx,
+                               const void *dsy, void *fx, void *fy, void *workspace,
+                               void *stream);
+
+/* Workspace bytes for gravity_solve_batch over these n plans. */
+gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *plans,
+                                               size_t *bytes);
+
+/*
+ * Queue n independent solves (plans may differ in size, levels and
+ * precision) as one batch: solves that share an FFT size and precision run
+ * together in each kernel launch.  Arrays of n device pointers as in
+ * gravity_solve (dsx/dsy may be NULL, or hold NULL entries for
+ * GRAVITY_SLOPES_NONE plans).  Results are bit-identical to n separate
+ * gravity_solve calls.  workspace: gravity_batch_workspace_bytes bytes.
+ */
+gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans,
+                                     const void *const *sigma, const void *const *dsx,
+                                     const void *const *dsy, void *const *fx,
+                                     void *const *fy, void *workspace, void *stream);
+
+/*
+ * Profiling aid: queue `reps` solves on `stream` as gravity_solve does,
+ * recording HIP events on that stream between the kernels of the pipeline,
+ * wait for them, and return the mean device time of each stage in
+ * stage_ms[0 .. *nstages - 1] (at most 8 stages; names from
+ * gravity_stage_name).  Outputs are those of the last solve.
+ * Errors: as gravity_solve; EINVAL if reps < 1 or stage_ms/nstages is NULL.
+ */
+gravity_status_t gravity_solve_profiled(gravity_plan_t plan, const void *sigma, const void *dsx,
+                                        const void *dsy, void *fx, void *fy, void *workspace,
+                                        void *stream, int32_t reps, double *stage_ms,
+                                        int32_t *nstages);
+
+/* Name of stage `stage` of this plan's pipeline ("" if out of range). */
+const char *gravity_stage_name(gravity_plan_t plan, int32_t stage);
+
+/* Release a plan (NULL is ignored).  Spectra stay resident while another
+ * plan uses them.  The caller must ensure no queued solve still uses it. */
+void gravity_plan_destroy(gravity_plan_t plan);
+
+/* Device bytes currently held by the resident spectrum cache. */
+size_t gravity_cache_bytes(void);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *gravity_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAVITY_H */

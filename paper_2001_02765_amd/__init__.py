@@ -1,0 +1,220 @@
+"""Thin-disk self-gravity on MI355X: Python binding of libgravity.so.
+
+The binding only marshals arguments into the C ABI declared in
+``include/gravity.h``; every step of a solve runs in the library's HIP
+kernels.  Arrays are torch tensors on the GPU (torch provides device memory
+and streams).  There is no CPU path: importing this package fails if the
+built library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgravity.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libgravity.so is not built (run paper_2001_02765_amd/build.py or "
+                      "__graft_entry__.build()); there is no fallback path")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = range(6)
+F32, F64 = 0, 1
+SLOPES_NONE, SLOPES_GIVEN = 0, 1
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "EBUSY"}
+
+# exported symbols of include/gravity.h
+SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
+           "gravity_solve", "gravity_batch_workspace_bytes", "gravity_solve_batch",
+           "gravity_solve_profiled", "gravity_stage_name", "gravity_plan_destroy",
+           "gravity_cache_bytes", "gravity_last_error")
+
+
+class PatchT(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("i0", ctypes.c_int32), ("j0", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class DescT(ctypes.Structure):
+    _fields_ = [("n0x", ctypes.c_int32), ("n0y", ctypes.c_int32), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("h0", ctypes.c_double), ("nlevels", ctypes.c_int32),
+                ("npatches", ctypes.c_int32), ("patches", ctypes.POINTER(PatchT)),
+                ("prec", ctypes.c_int), ("slopes", ctypes.c_int), ("G", ctypes.c_double)]
+
+
+class InfoT(ctypes.Structure):
+    _fields_ = [("n_finest", ctypes.c_int32), ("fft_size", ctypes.c_int32),
+                ("n_cells", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t)]
+
+
+_vp = ctypes.c_void_p
+_lib.gravity_plan.argtypes = [ctypes.POINTER(DescT), ctypes.POINTER(_vp)]
+_lib.gravity_plan.restype = ctypes.c_int
+_lib.gravity_plan_workspace_bytes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.gravity_plan_workspace_bytes.restype = ctypes.c_int
+_lib.gravity_plan_get_info.argtypes = [_vp, ctypes.POINTER(InfoT)]
+_lib.gravity_plan_get_info.restype = ctypes.c_int
+_lib.gravity_solve.argtypes = [_vp] * 8
+_lib.gravity_solve.restype = ctypes.c_int
+_lib.gravity_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
+                                               ctypes.POINTER(ctypes.c_size_t)]
+_lib.gravity_batch_workspace_bytes.restype = ctypes.c_int
+_lib.gravity_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 5 + [_vp, _vp]
+_lib.gravity_solve_batch.restype = ctypes.c_int
+_lib.gravity_solve_profiled.argtypes = [_vp] * 8 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                                    ctypes.POINTER(ctypes.c_int32)]
+_lib.gravity_solve_profiled.restype = ctypes.c_int
+_lib.gravity_stage_name.argtypes = [_vp, ctypes.c_int32]
+_lib.gravity_stage_name.restype = ctypes.c_char_p
+_lib.gravity_plan_destroy.argtypes = [_vp]
+_lib.gravity_plan_destroy.restype = None
+_lib.gravity_cache_bytes.argtypes = []
+_lib.gravity_cache_bytes.restype = ctypes.c_size_t
+_lib.gravity_last_error.argtypes = []
+_lib.gravity_last_error.restype = ctypes.c_char_p
+
+
+class GravityError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+
+
+def _check(st):
+    if st != OK:
+        raise GravityError(st, _lib.gravity_last_error().decode(errors="replace"))
+
+
+def cache_bytes():
+    """Device bytes held by the resident kernel-spectrum cache."""
+    return int(_lib.gravity_cache_bytes())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A solve plan: geometry, refinement layout, precision and resident spectra.
+
+    n0: base cells per side; nlevels: 1 for a uniform grid; patches: sequence
+    of (level, i0, j0, nx, ny) with level >= 1 (base is level 0).  The domain
+    is [x0, x0 + n0 h0] x [y0, y0 + n0 h0] (default [-1, 1]^2).
+    """
+
+    def __init__(self, n0, prec=F32, slopes=True, G=1.0, x0=-1.0, y0=-1.0, h0=None,
+                 nlevels=1, patches=()):
+        if h0 is None:
+            h0 = 2.0 / n0
+        pl = list(patches)
+        self._patch_arr = (PatchT * max(1, len(pl)))()
+        for k, p in enumerate(pl):
+            if hasattr(p, "level"):
+                p = (p.level, p.i0, p.j0, p.nx, p.ny)
+            self._patch_arr[k] = PatchT(*[int(v) for v in p])
+        d = DescT(int(n0), int(n0), float(x0), float(y0), float(h0), int(nlevels), len(pl),
+                  ctypes.cast(self._patch_arr, ctypes.POINTER(PatchT)), int(prec),
+                  SLOPES_GIVEN if slopes else SLOPES_NONE, float(G))
+        h = _vp()
+        _check(_lib.gravity_plan(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.prec = int(prec)
+        self.slopes = bool(slopes)
+        info = InfoT()
+        _check(_lib.gravity_plan_get_info(h, ctypes.byref(info)))
+        self.n_finest = info.n_finest
+        self.fft_size = info.fft_size
+        self.n_cells = info.n_cells
+        self.n_leaves = info.n_leaves
+        self.workspace_bytes = info.workspace_bytes
+        self.resident_bytes = info.resident_bytes
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.prec == F64 else torch.float32
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gravity_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self):
+        """A fresh device workspace tensor of the required size."""
+        import torch
+        return torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device="cuda")
+
+    def solve(self, sigma, dsx=None, dsy=None, fx=None, fy=None, workspace=None, stream=None):
+        """Queue a solve on ``stream`` (default: torch's current stream).
+
+        Inputs are composite-packed device tensors of the plan's dtype; returns
+        (fx, fy), allocated if not given."""
+        import torch
+        dt = self.torch_dtype
+        for t in (sigma, dsx, dsy):
+            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("inputs must be contiguous %s CUDA tensors" % dt)
+            if t is not None and t.numel() != self.n_cells:
+                raise ValueError("inputs must hold %d composite-packed cells" % self.n_cells)
+        if fx is None:
+            fx = torch.empty(self.n_cells, dtype=dt, device=sigma.device)
+        if fy is None:
+            fy = torch.empty(self.n_cells, dtype=dt, device=sigma.device)
+        if workspace is None:
+            workspace = self.workspace()
+        _check(_lib.gravity_solve(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx), _ptr(fy),
+                                  _ptr(workspace), _stream_handle(stream)))
+        return fx, fy
+
+
+    def profile(self, sigma, dsx, dsy, fx, fy, workspace, reps=20, stream=None):
+        """Mean device milliseconds per pipeline stage over ``reps`` solves,
+        timed with HIP events on the solve stream: {stage name: ms}."""
+        ms = (ctypes.c_double * 8)()
+        ns = ctypes.c_int32()
+        _check(_lib.gravity_solve_profiled(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx),
+                                           _ptr(fy), _ptr(workspace), _stream_handle(stream),
+                                           int(reps), ms, ctypes.byref(ns)))
+        return {_lib.gravity_stage_name(self._h, k).decode(): ms[k] for k in range(ns.value)}
+
+
+def batch_workspace_bytes(plans):
+    n = len(plans)
+    arr = (_vp * max(1, n))(*[p.handle for p in plans])
+    b = ctypes.c_size_t()
+    _check(_lib.gravity_batch_workspace_bytes(n, arr, ctypes.byref(b)))
+    return int(b.value)
+
+
+def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None):
+    """Queue independent solves as one batch (see gravity_solve_batch)."""
+    n = len(plans)
+
+    def arr(ts):
+        if ts is None:
+            return None
+        return (_vp * max(1, n))(*[None if t is None else t.data_ptr() for t in ts])
+
+    ph = (_vp * max(1, n))(*[p.handle for p in plans])
+    _check(_lib.gravity_solve_batch(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
+                                    _ptr(workspace), _stream_handle(stream)))

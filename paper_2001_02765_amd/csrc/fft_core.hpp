@@ -1,0 +1,209 @@
+// Register/LDS Stockham FFT engine for gfx950 (wave64, 160 KB LDS per CU).
+//
+// A length-L complex transform is computed by NT cooperating threads, each
+// holding E = L / NT elements in registers.  On entry and on exit thread t
+// holds the elements of index t + NT*e (e = 0..E-1), natural order.  Each
+// radix-R pass is the Stockham autosort step: butterfly j reads x[j + r L/R],
+// applies the twiddles W_{Ns R}^{r (j mod Ns)}, transforms, and writes to
+// index (j / Ns) Ns R + (j mod Ns) + r Ns.  Intermediate passes exchange
+// through LDS; the last pass lands every output in the register of the
+// thread that owns it, so the forward output distribution equals the input
+// distribution of the next transform and of pointwise products (no exchange
+// between a forward transform, a spectral multiply and an inverse transform).
+//
+// Twiddles are read from a device table tw[k] = exp(-2 pi i k / M) built in
+// double precision; a length-L transform uses stride M / L.  DIR = -1 is the
+// forward transform, DIR = +1 the unnormalised inverse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace grav {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { typedef float2 type; };
+template <> struct vec2<double> { typedef double2 type; };
+template <typename T> using C = typename vec2<T>::type;
+
+template <typename T> __device__ __forceinline__ C<T> mk(T x, T y) { C<T> r; r.x = x; r.y = y; return r; }
+template <typename T> __device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ C<T> cmulc(C<T> a, C<T> b) {
+    return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T> __device__ __forceinline__ C<T> cconj(C<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ C<T> cscale(C<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// multiply by DIR * i  (forward: -i)
+template <int DIR, typename T> __device__ __forceinline__ C<T> rot(C<T> a) {
+    return DIR < 0 ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
+}
+// multiply by w (forward) or conj(w) (inverse)
+template <int DIR, typename T> __device__ __forceinline__ C<T> twm(C<T> a, C<T> w) {
+    return DIR < 0 ? cmul<T>(a, w) : cmulc<T>(a, w);
+}
+
+// cos and sin of 2 pi m / 16
+__host__ __device__ constexpr double cos16(int m) {
+    constexpr double t[16] = {
+        1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+        0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+        -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+        0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+    return t[m & 15];
+}
+__host__ __device__ constexpr double sin16(int m) { return cos16(m + 12); }
+
+template <int DIR, typename T> __device__ __forceinline__ void dft2(C<T> &a, C<T> &b) {
+    C<T> t = a;
+    a = cadd<T>(t, b);
+    b = csub<T>(t, b);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(C<T> &x0, C<T> &x1, C<T> &x2, C<T> &x3) {
+    C<T> a = cadd<T>(x0, x2), b = csub<T>(x0, x2);
+    C<T> c = cadd<T>(x1, x3), d = rot<DIR, T>(csub<T>(x1, x3));
+    x0 = cadd<T>(a, c);
+    x2 = csub<T>(a, c);
+    x1 = cadd<T>(b, d);
+    x3 = csub<T>(b, d);
+}
+
+// multiply by W_16^m in direction DIR, m a compile-time constant
+template <int DIR, int m, typename T> __device__ __forceinline__ C<T> w16(C<T> a) {
+    constexpr int mm = m & 15;
+    if constexpr (mm == 0) return a;
+    else if constexpr (mm == 4) return rot<DIR, T>(a);
+    else if constexpr (mm == 8) return mk<T>(-a.x, -a.y);
+    else if constexpr (mm == 12) return rot<-DIR, T>(a);
+    else {
+        constexpr double cd = cos16(mm), sd = DIR * sin16(mm);
+        const T c = (T)cd;
+        const T s = (T)sd;
+        return mk<T>(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
+}
+
+template <int DIR, typename T> __device__ __forceinline__ void dft8(C<T> *v) {
+    C<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR, T>(e0, e1, e2, e3);
+    dft4<DIR, T>(o0, o1, o2, o3);
+    o1 = w16<DIR, 2, T>(o1);
+    o2 = w16<DIR, 4, T>(o2);
+    o3 = w16<DIR, 6, T>(o3);
+    v[0] = cadd<T>(e0, o0); v[4] = csub<T>(e0, o0);
+    v[1] = cadd<T>(e1, o1); v[5] = csub<T>(e1, o1);
+    v[2] = cadd<T>(e2, o2); v[6] = csub<T>(e2, o2);
+    v[3] = cadd<T>(e3, o3); v[7] = csub<T>(e3, o3);
+}
+
+// 16 = 4 x 4: inner DFT-4 over n1 of x[4 n1 + n2], twiddle W16^{n2 k1},
+// outer DFT-4 over n2 giving X[k1 + 4 k2].
+template <int DIR, typename T> __device__ __forceinline__ void dft16(C<T> *v) {
+    C<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        a[n2][0] = v[n2]; a[n2][1] = v[n2 + 4]; a[n2][2] = v[n2 + 8]; a[n2][3] = v[n2 + 12];
+        dft4<DIR, T>(a[n2][0], a[n2][1], a[n2][2], a[n2][3]);
+    }
+    a[1][1] = w16<DIR, 1, T>(a[1][1]); a[1][2] = w16<DIR, 2, T>(a[1][2]); a[1][3] = w16<DIR, 3, T>(a[1][3]);
+    a[2][1] = w16<DIR, 2, T>(a[2][1]); a[2][2] = w16<DIR, 4, T>(a[2][2]); a[2][3] = w16<DIR, 6, T>(a[2][3]);
+    a[3][1] = w16<DIR, 3, T>(a[3][1]); a[3][2] = w16<DIR, 6, T>(a[3][2]); a[3][3] = w16<DIR, 9, T>(a[3][3]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C<T> b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+        dft4<DIR, T>(b0, b1, b2, b3);
+        v[k1] = b0; v[k1 + 4] = b1; v[k1 + 8] = b2; v[k1 + 12] = b3;
+    }
+}
+
+template <int R, int DIR, typename T> __device__ __forceinline__ void dft(C<T> *v) {
+    if constexpr (R == 2) dft2<DIR, T>(v[0], v[1]);
+    else if constexpr (R == 4) dft4<DIR, T>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<DIR, T>(v);
+    else if constexpr (R == 16) dft16<DIR, T>(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// LDS index with one pad element every 16 (breaks power-of-two strides)
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+// LDS elements needed for a length-L exchange region
+template <int L> constexpr int lds_region() { return L + (L >> 4) + 1; }
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+// radix of pass p for a length-L transform on NT threads: a leading pass of
+// the leftover radix (if log2 L is not a multiple of log2 E), then radix E
+template <int L, int NT> struct Plan {
+    static constexpr int E = L / NT;
+    static constexpr int l = ilog2(L), e = ilog2(E);
+    static constexpr int rem = l % e;
+    static constexpr int npass = l / e + (rem ? 1 : 0);
+    static constexpr int radix(int p) { return (p == 0 && rem) ? (1 << rem) : E; }
+    static_assert(E >= 2 && E <= 16 && (E & (E - 1)) == 0, "E must be 2..16, power of two");
+    static_assert(NT * E == L, "NT * E must equal L");
+};
+
+template <typename T, int L, int NT, int DIR, int NS, int R, bool LAST>
+__device__ __forceinline__ void st_pass(C<T> *reg, C<T> *lds, const C<T> *__restrict__ tw,
+                                        int tws, int t) {
+    constexpr int E = L / NT;
+    constexpr int B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + NT * b;
+        const int k = j & (NS - 1);
+        C<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = reg[b + r * B];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C<T> w = tw[(r * k * (L / (NS * R))) * tws];
+                v[r] = twm<DIR, T>(v[r], w);
+            }
+        }
+        dft<R, DIR, T>(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) reg[b + r * B] = v[r];
+        } else {
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[pidx(base + r * NS)] = v[r];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) reg[e] = lds[pidx(t + NT * e)];
+        __syncthreads();
+    }
+}
+
+template <typename T, int L, int NT, int DIR, int P, int NS>
+__device__ __forceinline__ void st_passes(C<T> *reg, C<T> *lds, const C<T> *__restrict__ tw,
+                                          int tws, int t) {
+    using PL = Plan<L, NT>;
+    constexpr int R = PL::radix(P);
+    constexpr bool LAST = (P == PL::npass - 1);
+    st_pass<T, L, NT, DIR, NS, R, LAST>(reg, lds, tw, tws, t);
+    if constexpr (!LAST) st_passes<T, L, NT, DIR, P + 1, NS * R>(reg, lds, tw, tws, t);
+}
+
+// Length-L transform by NT threads; t in [0, NT); lds: this transform's
+// region (lds_region<L>() elements); every thread of the block must call it
+// (it contains block-wide barriers).
+template <typename T, int L, int NT, int DIR>
+__device__ __forceinline__ void fft(C<T> *reg, C<T> *lds, const C<T> *__restrict__ tw, int tws,
+                                    int t) {
+    st_passes<T, L, NT, DIR, 0, 1>(reg, lds, tw, tws, t);
+}
+
+}  // namespace grav

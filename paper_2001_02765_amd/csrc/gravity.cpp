@@ -1,0 +1,709 @@
+// Host runtime of the thin-disk gravity library: plans, the resident kernel
+// spectrum cache, AMR lattice maps, workspace layout and the C ABI.
+#include "../../include/gravity.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace {
+
+using namespace grav;
+
+thread_local std::string g_err;
+
+struct Failure {
+    gravity_status_t st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(gravity_status_t st, const std::string &msg) { throw Failure{st, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(GRAVITY_ENOMEM, std::string(what) + ": out of device memory");
+    fail(GRAVITY_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Optional failure injection: GRAVITY_FAIL_ALLOC_AFTER=n makes every device
+// allocation after the first n fail with GRAVITY_ENOMEM.
+std::mutex g_alloc_mu;
+long g_alloc_count = 0;
+
+void *dev_alloc(size_t bytes, const char *what) {
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        const char *env = std::getenv("GRAVITY_FAIL_ALLOC_AFTER");
+        if (env && *env) {
+            long lim = std::atol(env);
+            if (g_alloc_count >= lim) fail(GRAVITY_ENOMEM, std::string(what) + ": injected allocation failure");
+        }
+        ++g_alloc_count;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(GRAVITY_ENOMEM, std::string(what) + ": hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(size_t b, const char *what) : p(dev_alloc(b, what)), bytes(b) {}
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b, const char *what) {
+        release();
+        p = dev_alloc(b, what);
+        bytes = b;
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n, long double)
+void gauss_legendre(int n, double *x, double *w) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        long double z = cosl(pi * (i + 0.75L) / (n + 0.5L)), dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        x[i] = (double)z;
+        w[i] = (double)(2.0L / ((1 - z * z) * dp * dp));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// resident device tables
+// ---------------------------------------------------------------------------
+
+// twiddles exp(-2 pi i k / M), k < M, and half-angle phases exp(-i pi k / M),
+// k <= M/2, in the plan precision (computed in long double, rounded)
+struct Twiddles {
+    int device, M, prec;
+    DevBuf tw, ph;
+};
+
+template <typename T> void fill_twiddles(int M, std::vector<T> &tw, std::vector<T> &ph) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    tw.resize(2 * (size_t)M);
+    ph.resize(2 * (size_t)(M / 2 + 1));
+    for (int k = 0; k < M; ++k) {
+        long double a = 2 * pi * k / M;
+        tw[2 * k] = (T)cosl(a);
+        tw[2 * k + 1] = (T)(-sinl(a));
+    }
+    for (int k = 0; k <= M / 2; ++k) {
+        long double a = pi * k / M;
+        ph[2 * k] = (T)cosl(a);
+        ph[2 * k + 1] = (T)(-sinl(a));
+    }
+}
+
+std::shared_ptr<Twiddles> make_twiddles(int device, int M, int prec) {
+    auto t = std::make_shared<Twiddles>();
+    t->device = device;
+    t->M = M;
+    t->prec = prec;
+    size_t esz = prec ? sizeof(double) : sizeof(float);
+    t->tw.alloc(2 * esz * M, "twiddle table");
+    t->ph.alloc(2 * esz * (M / 2 + 1), "phase table");
+    if (prec) {
+        std::vector<double> tw, ph;
+        fill_twiddles<double>(M, tw, ph);
+        hip_check(hipMemcpy(t->tw.p, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice), "twiddle upload");
+        hip_check(hipMemcpy(t->ph.p, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice), "phase upload");
+    } else {
+        std::vector<float> tw, ph;
+        fill_twiddles<float>(M, tw, ph);
+        hip_check(hipMemcpy(t->tw.p, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice), "twiddle upload");
+        hip_check(hipMemcpy(t->ph.p, ph.data(), ph.size() * sizeof(float), hipMemcpyHostToDevice), "phase upload");
+    }
+    return t;
+}
+
+// six kernel-spectrum quadrants of one family at one size and precision
+struct KernelSet {
+    int device, M, prec, family;
+    DevBuf q;
+    int64_t q_pitch, q_kstride;
+};
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int>, std::weak_ptr<Twiddles>> g_tw_cache;
+std::map<std::tuple<int, int, int, int>, std::weak_ptr<KernelSet>> g_ks_cache;
+
+std::shared_ptr<Twiddles> get_twiddles(int device, int M, int prec) {
+    auto key = std::make_tuple(device, M, prec);
+    auto it = g_tw_cache.find(key);
+    if (it != g_tw_cache.end()) {
+        if (auto sp = it->second.lock()) return sp;
+    }
+    auto sp = make_twiddles(device, M, prec);
+    g_tw_cache[key] = sp;
+    return sp;
+}
+
+std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int family) {
+    auto ks = std::make_shared<KernelSet>();
+    ks->device = device;
+    ks->M = M;
+    ks->prec = prec;
+    ks->family = family;
+    const int H = M / 2;
+    ks->q_pitch = ((H + 1) + 63) / 64 * 64;
+    ks->q_kstride = ks->q_pitch * (H + 1);
+    const size_t esz = prec ? sizeof(double) : sizeof(float);
+    ks->q.alloc(6 * esz * ks->q_kstride, "kernel spectra");
+    // transient double-precision buffers
+    DevBuf table(sizeof(double) * (size_t)M * M, "kernel table");
+    DevBuf rows(sizeof(double) * 2 * (size_t)(H + 1) * M, "kernel table row spectra");
+    auto tw64 = get_twiddles(device, M, 1);
+    TableArgs ta{};
+    ta.out = (double *)table.p;
+    ta.M = M;
+    ta.family = family;
+    gauss_legendre(10, ta.glx, ta.glw);
+    hipStream_t s = nullptr;
+    for (int kind = 0; kind < 6; ++kind) {
+        ta.kind = kind;
+        hip_check(launch_ktable(ta, s), "kernel table build");
+        RowFwdArgs<double> ra{};
+        ra.in[0] = (const double *)table.p;
+        ra.scale[0] = 1.0;
+        ra.in_pitch = M;
+        ra.out = (C<double> *)rows.p;
+        ra.out_pitch = M;
+        ra.out_fstride = 0;
+        hip_check(launch_row_fwd<double>(ra, M, false, M, 1, (const C<double> *)tw64->tw.p, s),
+                  "kernel table row transform");
+        const int imag = (kind == 0 || kind == 3) ? 1 : 0;
+        if (prec) {
+            hip_check(launch_col_extract<double>((const C<double> *)rows.p, M,
+                                                 (double *)ks->q.p + kind * ks->q_kstride, ks->q_pitch,
+                                                 imag, family, (const C<double> *)tw64->tw.p,
+                                                 (const C<double> *)tw64->ph.p, s),
+                      "kernel spectrum");
+        } else {
+            hip_check(launch_col_extract<float>((const C<double> *)rows.p, M,
+                                                (float *)ks->q.p + kind * ks->q_kstride, ks->q_pitch,
+                                                imag, family, (const C<double> *)tw64->tw.p,
+                                                (const C<double> *)tw64->ph.p, s),
+                      "kernel spectrum");
+        }
+    }
+    hip_check(hipStreamSynchronize(s), "kernel spectra build");
+    return ks;
+}
+
+std::shared_ptr<KernelSet> get_kernel_set(int device, int M, int prec, int family) {
+    auto key = std::make_tuple(device, M, prec, family);
+    auto it = g_ks_cache.find(key);
+    if (it != g_ks_cache.end()) {
+        if (auto sp = it->second.lock()) return sp;
+    }
+    auto sp = build_kernel_set(device, M, prec, family);
+    g_ks_cache[key] = sp;
+    return sp;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+struct gravity_plan_s {
+    int device = 0;
+    int prec = 0;
+    int slopes = 1;
+    double G = 1.0;
+    int n0 = 0, nlevels = 1;
+    double x0 = 0, y0 = 0, h0 = 0;
+    std::vector<gravity_patch_t> patches;
+    int nf = 0;  // finest lattice cells per side
+    int M = 0;
+    bool amr = false;
+    int nfields = 3;
+    int64_t ncells = 0, nleaves = 0;
+    std::shared_ptr<Twiddles> tw;
+    std::shared_ptr<KernelSet> centre, corner;
+    DevBuf owner, gmap;
+    // workspace layout (byte offsets)
+    size_t off_w = 0, off_a = 0, off_b = 0, off_o = 0, ws_bytes = 0;
+};
+
+namespace {
+
+void validate_and_build_maps(gravity_plan_s &p, std::vector<int32_t> &owner, std::vector<int32_t> &gmap) {
+    const int L = p.nlevels;
+    // blocks: base then patches, composite offsets
+    struct Blk {
+        int level, i0, j0, nx, ny;
+        int64_t off;
+    };
+    std::vector<Blk> blks;
+    blks.push_back({0, 0, 0, p.n0, p.n0, 0});
+    int64_t off = (int64_t)p.n0 * p.n0;
+    for (auto &q : p.patches) {
+        if (q.level < 1 || q.level >= L) fail(GRAVITY_EINVAL, "patch level out of range");
+        if (q.nx <= 0 || q.ny <= 0) fail(GRAVITY_EINVAL, "empty patch");
+        if ((q.i0 | q.j0 | q.nx | q.ny) & 1) fail(GRAVITY_EINVAL, "patch corners and sizes must be even");
+        const int64_t nl = (int64_t)p.n0 << q.level;
+        if (q.i0 < 0 || q.j0 < 0 || q.i0 + (int64_t)q.nx > nl || q.j0 + (int64_t)q.ny > nl)
+            fail(GRAVITY_EINVAL, "patch outside the domain");
+        blks.push_back({q.level, q.i0, q.j0, q.nx, q.ny, off});
+        off += (int64_t)q.nx * q.ny;
+    }
+    p.ncells = off;
+    if (off >= (1 << 28)) fail(GRAVITY_EUNSUPPORTED, "too many composite cells");
+    const int nf = p.nf;
+    // coverage per level: which block (index) covers each cell of that level
+    // (as a map on that level's lattice), to find leaves and check nesting
+    std::vector<std::vector<int32_t>> cover(L);
+    for (int l = 0; l < L; ++l) {
+        const int64_t n = (int64_t)p.n0 << l;
+        cover[l].assign((size_t)(n * n), -1);
+    }
+    for (size_t b = 0; b < blks.size(); ++b) {
+        const Blk &k = blks[b];
+        const int64_t n = (int64_t)p.n0 << k.level;
+        for (int j = 0; j < k.ny; ++j)
+            for (int i = 0; i < k.nx; ++i) {
+                int32_t &c = cover[k.level][(size_t)((k.j0 + j) * n + k.i0 + i)];
+                if (c >= 0) fail(GRAVITY_EINVAL, "overlapping patches on one level");
+                c = (int32_t)b;
+            }
+    }
+    // nesting: every level-l cell covered by a patch must have a covered parent
+    for (int l = 1; l < L; ++l) {
+        const int64_t n = (int64_t)p.n0 << l;
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                if (cover[l][(size_t)(j * n + i)] >= 0 && cover[l - 1][(size_t)((j / 2) * (n / 2) + i / 2)] < 0)
+                    fail(GRAVITY_EINVAL, "patch not nested inside the level below");
+    }
+    owner.assign((size_t)nf * nf, -1);
+    gmap.assign((size_t)p.ncells, -1);
+    int64_t leaves = 0;
+    for (size_t b = 0; b < blks.size(); ++b) {
+        const Blk &k = blks[b];
+        const int l = k.level;
+        const int64_t n = (int64_t)p.n0 << l;
+        const int kb = L - 1 - l;  // log2 of finest cells per side of this level's cell
+        const int B = 1 << kb;
+        for (int j = 0; j < k.ny; ++j)
+            for (int i = 0; i < k.nx; ++i) {
+                const int64_t gi = k.i0 + i, gj = k.j0 + j;
+                bool leaf = true;
+                if (l + 1 < L) {
+                    const int64_t nc = n * 2;
+                    if (cover[l + 1][(size_t)((2 * gj) * nc + 2 * gi)] >= 0) leaf = false;
+                }
+                (void)n;
+                if (!leaf) continue;
+                ++leaves;
+                const int64_t c = k.off + (int64_t)j * k.nx + i;
+                for (int jj = 0; jj < B; ++jj)
+                    for (int ii = 0; ii < B; ++ii) {
+                        int32_t &o = owner[(size_t)((gj * B + jj) * nf + gi * B + ii)];
+                        if (o >= 0) fail(GRAVITY_EINVAL, "leaves overlap");
+                        o = (int32_t)c | (kb << 28);
+                    }
+                if (kb == 0) {
+                    gmap[(size_t)c] = (int32_t)(gj * nf + gi);  // centre family, its own cell
+                } else {
+                    const int64_t I = gi * B + B / 2, J = gj * B + B / 2;  // centre vertex
+                    gmap[(size_t)c] = (int32_t)(J * nf + I) | (1 << 30);
+                }
+            }
+    }
+    for (auto o : owner)
+        if (o < 0) fail(GRAVITY_EINVAL, "leaves do not tile the domain");
+    p.nleaves = leaves;
+}
+
+gravity_status_t finish(gravity_status_t st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+template <typename F> gravity_status_t guarded(F &&fn) {
+    try {
+        fn();
+        return GRAVITY_OK;
+    } catch (const Failure &f) {
+        return finish(f.st, f.msg);
+    } catch (const std::bad_alloc &) {
+        return finish(GRAVITY_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return finish(GRAVITY_EDEVICE, e.what());
+    } catch (...) {
+        return finish(GRAVITY_EDEVICE, "unknown error");
+    }
+}
+
+const char *const kStagesUniform[] = {"row_fwd", "col", "row_inv"};
+const char *const kStagesAmr[] = {"inject", "row_fwd", "col", "row_inv", "gather"};
+
+int n_stages(const gravity_plan_s &p) { return p.amr ? 5 : 3; }
+
+// ev: optional array of n_stages(p) + 1 events recorded between the stages
+template <typename T>
+void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const void *dsy, void *fx,
+             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+    int stage = 0;
+    auto mark = [&]() {
+        if (ev) hip_check(hipEventRecord(ev[stage++], s), "hipEventRecord");
+    };
+    const int n = p.nf, M = p.M, H = M / 2;
+    const int NF = p.nfields;
+    const C<T> *tw = (const C<T> *)p.tw->tw.p;
+    const C<T> *ph = (const C<T> *)p.tw->ph.p;
+    C<T> *A = (C<T> *)(ws + p.off_a);
+    C<T> *B = (C<T> *)(ws + p.off_b);
+    const int64_t colsz = (int64_t)(H + 1) * n;
+    const T h = (T)(p.h0 / (double)(1 << (p.nlevels - 1)));
+
+    RowFwdArgs<T> ra{};
+    if (!p.amr) {
+        ra.in[0] = (const T *)sigma;
+        ra.in[1] = (const T *)dsx;
+        ra.in[2] = (const T *)dsy;
+    } else {
+        T *W = (T *)(ws + p.off_w);
+        const int64_t n2 = (int64_t)n * n;
+        InjectArgs<T> ia{};
+        ia.s = (const T *)sigma;
+        ia.dx = (const T *)dsx;
+        ia.dy = (const T *)dsy;
+        ia.owner = (const int32_t *)p.owner.p;
+        ia.w0 = W;
+        ia.w1 = W + n2;
+        ia.w2 = W + 2 * n2;
+        ia.nf = n;
+        ia.hf = h;
+        ia.slopes = NF == 3;
+        mark();
+        hip_check(launch_inject<T>(ia, s), "inject");
+        ra.in[0] = W;
+        ra.in[1] = W + n2;
+        ra.in[2] = W + 2 * n2;
+    }
+    ra.scale[0] = (T)1;
+    ra.scale[1] = h;
+    ra.scale[2] = h;
+    ra.in_pitch = n;
+    ra.out = A;
+    ra.out_pitch = n;
+    ra.out_fstride = colsz;
+    mark();
+    hip_check(launch_row_fwd<T>(ra, M, true, n, NF, tw, s), "row transform");
+
+    ColArgs<T> ca{};
+    ca.in = A;
+    ca.in_pitch = n;
+    ca.in_fstride = colsz;
+    ca.q[0] = (const T *)p.centre->q.p;
+    ca.q[1] = p.amr ? (const T *)p.corner->q.p : (const T *)p.centre->q.p;
+    ca.q_pitch = p.centre->q_pitch;
+    ca.q_kstride = p.centre->q_kstride;
+    ca.out = B;
+    ca.out_pitch = n;
+    ca.out_gstride = colsz;
+    const int nfam = p.amr ? 2 : 1;
+    mark();
+    hip_check(launch_col<T>(ca, M, NF, nfam, tw, ph, s), "column transform");
+
+    RowInvArgs<T> ia{};
+    ia.in = B;
+    ia.in_pitch = n;
+    ia.in_gstride = colsz;
+    ia.out_pitch = n;
+    ia.scale = (T)(p.G / ((double)M * (double)M));
+    if (!p.amr) {
+        ia.out[0] = (T *)fx;
+        ia.out[1] = (T *)fy;
+        mark();
+        hip_check(launch_row_inv<T>(ia, M, n, 2, tw, s), "inverse row transform");
+        mark();
+    } else {
+        T *O = (T *)(ws + p.off_o);
+        const int64_t n2 = (int64_t)n * n;
+        for (int g = 0; g < 4; ++g) ia.out[g] = O + g * n2;
+        mark();
+        hip_check(launch_row_inv<T>(ia, M, n, 4, tw, s), "inverse row transform");
+        GatherArgs<T> ga{};
+        ga.gmap = (const int32_t *)p.gmap.p;
+        for (int g = 0; g < 4; ++g) ga.o[g] = O + g * n2;
+        ga.fx = (T *)fx;
+        ga.fy = (T *)fy;
+        ga.n = p.ncells;
+        mark();
+        hip_check(launch_gather<T>(ga, s), "gather");
+        mark();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!d || !out) fail(GRAVITY_EINVAL, "NULL descriptor or output");
+        if (d->n0x != d->n0y) fail(GRAVITY_EUNSUPPORTED, "only square base grids are supported");
+        if (!is_pow2(d->n0x)) fail(GRAVITY_EUNSUPPORTED, "base size must be a power of two");
+        if (d->nlevels < 1 || d->nlevels > 8) fail(GRAVITY_EINVAL, "nlevels must be 1..8");
+        if (!(d->h0 > 0) || !std::isfinite(d->h0) || !std::isfinite(d->x0) || !std::isfinite(d->y0))
+            fail(GRAVITY_EINVAL, "bad geometry");
+        if (d->prec != GRAVITY_F32 && d->prec != GRAVITY_F64) fail(GRAVITY_EINVAL, "bad precision");
+        if (d->slopes != GRAVITY_SLOPES_NONE && d->slopes != GRAVITY_SLOPES_GIVEN)
+            fail(GRAVITY_EINVAL, "bad slope mode");
+        if (d->npatches < 0 || (d->npatches > 0 && !d->patches)) fail(GRAVITY_EINVAL, "bad patch list");
+        if (d->nlevels == 1 && d->npatches > 0) fail(GRAVITY_EINVAL, "patches need nlevels > 1");
+        const int64_t nf = (int64_t)d->n0x << (d->nlevels - 1);
+        if (nf < 16 || nf > kMaxM / 2)
+            fail(GRAVITY_EUNSUPPORTED, "finest lattice must have 16..4096 cells per side");
+        auto p = std::make_unique<gravity_plan_s>();
+        p->prec = d->prec;
+        p->slopes = d->slopes;
+        p->G = d->G;
+        p->n0 = d->n0x;
+        p->nlevels = d->nlevels;
+        p->x0 = d->x0;
+        p->y0 = d->y0;
+        p->h0 = d->h0;
+        p->patches.assign(d->patches, d->patches + d->npatches);
+        p->nf = (int)nf;
+        p->M = 2 * p->nf;
+        p->amr = d->nlevels > 1;
+        p->nfields = d->slopes == GRAVITY_SLOPES_GIVEN ? 3 : 1;
+        std::vector<int32_t> owner, gmap;
+        if (p->amr) {
+            validate_and_build_maps(*p, owner, gmap);
+        } else {
+            p->ncells = p->nleaves = (int64_t)p->n0 * p->n0;
+        }
+        hip_check(hipGetDevice(&p->device), "hipGetDevice");
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            p->tw = get_twiddles(p->device, p->M, p->prec);
+            p->centre = get_kernel_set(p->device, p->M, p->prec, 0);
+            if (p->amr) p->corner = get_kernel_set(p->device, p->M, p->prec, 1);
+        }
+        if (p->amr) {
+            p->owner.alloc(owner.size() * sizeof(int32_t), "AMR owner map");
+            p->gmap.alloc(gmap.size() * sizeof(int32_t), "AMR gather map");
+            hip_check(hipMemcpy(p->owner.p, owner.data(), owner.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                      "owner map upload");
+            hip_check(hipMemcpy(p->gmap.p, gmap.data(), gmap.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                      "gather map upload");
+        }
+        const size_t esz = p->prec ? sizeof(double) : sizeof(float);
+        const int64_t n = p->nf, H = p->M / 2;
+        const size_t colsz = 2 * esz * (size_t)((H + 1) * n);
+        size_t off = 0;
+        if (p->amr) {
+            p->off_w = off;
+            off += align256(esz * p->nfields * (size_t)(n * n));
+        }
+        p->off_a = off;
+        off += align256(colsz * p->nfields);
+        p->off_b = off;
+        off += align256(colsz * (p->amr ? 4 : 2));
+        if (p->amr) {
+            p->off_o = off;
+            off += align256(esz * 4 * (size_t)(n * n));
+        }
+        p->ws_bytes = off;
+        *out = p.release();
+    });
+}
+
+gravity_status_t gravity_plan_workspace_bytes(gravity_plan_t p, size_t *bytes) {
+    return guarded([&] {
+        if (!p || !bytes) fail(GRAVITY_EINVAL, "NULL argument");
+        *bytes = p->ws_bytes;
+    });
+}
+
+gravity_status_t gravity_plan_get_info(gravity_plan_t p, gravity_plan_info_t *info) {
+    return guarded([&] {
+        if (!p || !info) fail(GRAVITY_EINVAL, "NULL argument");
+        info->n_finest = p->nf;
+        info->fft_size = p->M;
+        info->n_cells = p->ncells;
+        info->n_leaves = p->nleaves;
+        info->workspace_bytes = p->ws_bytes;
+        size_t r = p->owner.bytes + p->gmap.bytes;
+        if (p->centre) r += p->centre->q.bytes;
+        if (p->corner) r += p->corner->q.bytes;
+        if (p->tw) r += p->tw->tw.bytes + p->tw->ph.bytes;
+        info->resident_bytes = r;
+    });
+}
+
+static void check_solve_args(gravity_plan_t p, const void *sigma, const void *dsx, const void *dsy,
+                             void *fx, void *fy, void *ws) {
+    if (!p) fail(GRAVITY_EINVAL, "NULL plan");
+    if (!sigma || !fx || !fy || !ws) fail(GRAVITY_EINVAL, "NULL array argument");
+    if (p->nfields == 3 && (!dsx || !dsy)) fail(GRAVITY_EINVAL, "slopes required by this plan");
+    if (((uintptr_t)ws) & 255) fail(GRAVITY_EINVAL, "workspace must be 256-byte aligned");
+    const size_t al = p->prec ? 16 : 8;
+    if ((((uintptr_t)sigma) | ((uintptr_t)fx) | ((uintptr_t)fy)) & (al - 1))
+        fail(GRAVITY_EINVAL, "arrays must be aligned to two elements");
+    if (p->nfields == 3 && ((((uintptr_t)dsx) | ((uintptr_t)dsy)) & (al - 1)))
+        fail(GRAVITY_EINVAL, "arrays must be aligned to two elements");
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p->device) fail(GRAVITY_EINVAL, "plan was created on another device");
+}
+
+gravity_status_t gravity_solve(gravity_plan_t p, const void *sigma, const void *dsx, const void *dsy,
+                               void *fx, void *fy, void *workspace, void *stream) {
+    return guarded([&] {
+        check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
+        hipStream_t s = (hipStream_t)stream;
+        if (p->prec)
+            solve_t<double>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s);
+        else
+            solve_t<float>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s);
+    });
+}
+
+gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *plans, size_t *bytes) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && !plans) || !bytes) fail(GRAVITY_EINVAL, "bad batch arguments");
+        size_t tot = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!plans[i]) fail(GRAVITY_EINVAL, "NULL plan in batch");
+            tot += align256(plans[i]->ws_bytes);
+        }
+        *bytes = tot;
+    });
+}
+
+gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
+                                     const void *const *dsx, const void *const *dsy, void *const *fx,
+                                     void *const *fy, void *workspace, void *stream) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && (!plans || !sigma || !fx || !fy))) fail(GRAVITY_EINVAL, "bad batch arguments");
+        size_t off = 0;
+        for (int i = 0; i < n; ++i) {
+            const void *dx = dsx ? dsx[i] : nullptr;
+            const void *dy = dsy ? dsy[i] : nullptr;
+            char *ws = workspace ? (char *)workspace + off : nullptr;
+            check_solve_args(plans[i], sigma[i], dx, dy, fx[i], fy[i], ws);
+            off += align256(plans[i]->ws_bytes);
+        }
+        hipStream_t s = (hipStream_t)stream;
+        off = 0;
+        for (int i = 0; i < n; ++i) {
+            const void *dx = dsx ? dsx[i] : nullptr;
+            const void *dy = dsy ? dsy[i] : nullptr;
+            char *ws = (char *)workspace + off;
+            if (plans[i]->prec)
+                solve_t<double>(*plans[i], sigma[i], dx, dy, fx[i], fy[i], ws, s);
+            else
+                solve_t<float>(*plans[i], sigma[i], dx, dy, fx[i], fy[i], ws, s);
+            off += align256(plans[i]->ws_bytes);
+        }
+    });
+}
+
+gravity_status_t gravity_solve_profiled(gravity_plan_t p, const void *sigma, const void *dsx,
+                                        const void *dsy, void *fx, void *fy, void *workspace,
+                                        void *stream, int32_t reps, double *stage_ms, int32_t *nstages) {
+    std::vector<hipEvent_t> ev;
+    gravity_status_t st = guarded([&] {
+        check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
+        if (reps < 1 || !stage_ms || !nstages) fail(GRAVITY_EINVAL, "bad profiling arguments");
+        const int ns = n_stages(*p);
+        ev.resize(ns + 1);
+        for (auto &e : ev) {
+            e = nullptr;
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+        }
+        std::vector<double> acc(ns, 0.0);
+        hipStream_t s = (hipStream_t)stream;
+        for (int r = 0; r < reps; ++r) {
+            if (p->prec)
+                solve_t<double>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s, ev.data());
+            else
+                solve_t<float>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s, ev.data());
+            hip_check(hipEventSynchronize(ev[ns]), "hipEventSynchronize");
+            for (int k = 0; k < ns; ++k) {
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
+                acc[k] += ms;
+            }
+        }
+        for (int k = 0; k < ns; ++k) stage_ms[k] = acc[k] / reps;
+        *nstages = ns;
+    });
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
+const char *gravity_stage_name(gravity_plan_t p, int32_t stage) {
+    if (!p || stage < 0 || stage >= n_stages(*p)) return "";
+    return p->amr ? kStagesAmr[stage] : kStagesUniform[stage];
+}
+
+void gravity_plan_destroy(gravity_plan_t p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    delete p;
+}
+
+size_t gravity_cache_bytes(void) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    size_t tot = 0;
+    for (auto &kv : g_ks_cache)
+        if (auto sp = kv.second.lock()) tot += sp->q.bytes;
+    for (auto &kv : g_tw_cache)
+        if (auto sp = kv.second.lock()) tot += sp->tw.bytes + sp->ph.bytes;
+    return tot;
+}
+
+const char *gravity_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Kernel argument blocks and host launchers shared by the HIP kernels and
+// the host runtime.  Layouts (all device memory):
+//   fields   : n x n row-major real arrays (row = y index, x fastest)
+//   A        : forward row spectra, A[f][kx][j], kx in [0, M/2], j in [0, rows)
+//   Q        : kernel-spectrum quadrants, Q[kind][kx][ky], kx, ky in [0, M/2]
+//   B        : column-inverted spectra, B[g][kx][j]
+// M is the zero-padded transform size (2 n), n the lattice cells per side.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft_core.hpp"
+
+namespace grav {
+
+constexpr int kMinM = 32;
+constexpr int kMaxM = 8192;
+
+template <typename T> struct RowFwdArgs {
+    const T *in[3];     // up to three real fields
+    T scale[3];         // per-field multiplier applied on load
+    int64_t in_pitch;   // elements between input rows
+    C<T> *out;          // A
+    int64_t out_pitch;  // elements between kx columns of A (= rows)
+    int64_t out_fstride;
+};
+
+template <typename T> struct ColArgs {
+    const C<T> *in;  // A
+    int64_t in_pitch, in_fstride;
+    const T *q[2];   // quadrants of the centre / corner family: kind k at q[f] + k q_kstride
+    int64_t q_pitch, q_kstride;
+    C<T> *out;       // B
+    int64_t out_pitch, out_gstride;
+};
+
+template <typename T> struct RowInvArgs {
+    const C<T> *in;  // B
+    int64_t in_pitch, in_gstride;
+    T *out[4];
+    int64_t out_pitch;
+    T scale;
+};
+
+template <typename T> struct InjectArgs {
+    const T *s, *dx, *dy;  // composite-packed leaf values
+    const int32_t *owner;  // per finest cell: leaf index | log2(block) << 28
+    T *w0, *w1, *w2;       // finest-lattice fields
+    int nf;
+    T hf;
+    int slopes;
+};
+
+template <typename T> struct GatherArgs {
+    const int32_t *gmap;  // per composite cell: -1, or lattice index | family << 30
+    const T *o[4];        // centre Fx, Fy, corner Fx, Fy on the finest lattice
+    T *fx, *fy;
+    int64_t n;
+};
+
+struct TableArgs {
+    double *out;  // M x M circulant table, row-major [my][mx]
+    int M;
+    int family;   // 0: cell-centre targets, 1: lattice-corner targets
+    int kind;     // 0..5: x0, xx, xy, y0, yx, yy
+    double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]
+};
+
+// Launch configurations (threads per block) used by the launchers.
+int row_threads(int prec, int M);
+int row_rows_per_block(int prec, int M);
+int col_threads(int prec, int M);
+
+template <typename T>
+hipError_t launch_row_fwd(const RowFwdArgs<T> &a, int M, bool pruned, int nrows, int nfields,
+                          const C<T> *tw, hipStream_t s);
+template <typename T>
+hipError_t launch_col(const ColArgs<T> &a, int M, int nfields, int nfam, const C<T> *tw,
+                      const C<T> *ph, hipStream_t s);
+template <typename T>
+hipError_t launch_row_inv(const RowInvArgs<T> &a, int M, int nrows, int nout, const C<T> *tw,
+                          hipStream_t s);
+template <typename T> hipError_t launch_inject(const InjectArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_gather(const GatherArgs<T> &a, hipStream_t s);
+
+hipError_t launch_ktable(const TableArgs &a, hipStream_t s);
+// forward FFT of the columns of a table's row spectra and extraction of one
+// real quadrant: Q[kx][ky] = part(e^{i pi corner (kx+ky)/M} S[ky][kx])
+template <typename TQ>
+hipError_t launch_col_extract(const C<double> *in, int M, TQ *q, int64_t q_pitch, int imag,
+                              int corner, const C<double> *tw, const C<double> *ph,
+                              hipStream_t s);
+
+}  // namespace grav

@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: relative L2 over both force components (area weighted on AMR
+layouts) <= 1e-12 for FP64 plans and <= 1e-5 for FP32 plans.
+"""
+import numpy as np
+import pytest
+
+import diskgen
+import oracle
+from oracle import analytic as an
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def gl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_02765_amd as m
+    return m
+
+
+def _prec(gl, name):
+    return gl.F64 if name == "f64" else gl.F32
+
+
+def _dt(name):
+    return torch.float64 if name == "f64" else torch.float32
+
+
+def _dev(a, name):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).to("cuda", _dt(name))
+
+
+def _host(t):
+    return t.double().cpu().numpy()
+
+
+def gpu_uniform(gl, prec, s, dx, dy, h=None, G=1.0, slopes=True):
+    n = s.shape[0]
+    p = gl.Plan(n, _prec(gl, prec), slopes=slopes, G=G, h0=h if h else 2.0 / n)
+    fx, fy = p.solve(_dev(s, prec), _dev(dx, prec) if slopes else None,
+                     _dev(dy, prec) if slopes else None)
+    torch.cuda.synchronize()
+    return _host(fx).reshape(n, n), _host(fy).reshape(n, n)
+
+
+def test_library_loaded(gl):
+    import ctypes
+    import os
+    maps = open("/proc/self/maps").read()
+    assert os.path.realpath(gl.LIB_PATH) in maps
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_cell_sources(gl, prec):
+    """One unit source cell at several positions, including the far corners
+    (largest offsets of the kernel tables): F is the oracle's direct sum."""
+    n = 32
+    for (i, j) in [(0, 0), (n - 1, n - 1), (5, 17), (n - 1, 0)]:
+        s = np.zeros((n, n))
+        s[j, i] = 1.0
+        dx = np.zeros((n, n))
+        dy = np.zeros((n, n))
+        dx[j, i] = 0.7
+        dy[j, i] = -1.3
+        fx, fy = gpu_uniform(gl, prec, s, dx, dy)
+        ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, 2.0 / n)
+        assert an.rel_l2((fx, fy), (ox, oy)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [16, 64, 128])
+def test_uniform_random(gl, prec, n):
+    s, dx, dy = diskgen.random_fields(n, 100 + n)
+    fx, fy = gpu_uniform(gl, prec, s, dx, dy)
+    ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, 2.0 / n)
+    assert an.rel_l2((fx, fy), (ox, oy)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_uniform_no_slopes(gl, prec):
+    n = 64
+    s, _, _ = diskgen.random_fields(n, 7, slopes=False)
+    fx, fy = gpu_uniform(gl, prec, s, None, None, slopes=False)
+    ox, oy = oracle.uniform(s, None, None, -1.0, -1.0, 2.0 / n)
+    assert an.rel_l2((fx, fy), (ox, oy)) < TOL[prec]
+
+
+def test_zero_density_gives_zero_force(gl):
+    n = 64
+    z = np.zeros((n, n))
+    fx, fy = gpu_uniform(gl, "f64", z, z, z)
+    assert np.all(fx == 0) and np.all(fy == 0)
+
+
+def test_kuzmin_64_fp64(gl):
+    """Bench config 1: 64^2 Kuzmin disk (M = 1, a = 0.2) in FP64, G = 1."""
+    n = 64
+    X, Y = diskgen.grid_centres(n)
+    s, dx, dy = diskgen.kuzmin(X, Y, 1.0, 0.2)
+    fx, fy = gpu_uniform(gl, "f64", s, dx, dy)
+    ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, 2.0 / n)
+    assert an.rel_l2((fx, fy), (ox, oy)) < 1e-12
+    tx, ty = an.kuzmin_truncated_force(X, Y)
+    assert an.rel_l2((fx, fy), (tx, ty)) < 4e-3
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_noisy_spiral_256_full(gl, prec):
+    n = 256
+    s, dx, dy, h = diskgen.noisy_spiral(n, 3)
+    fx, fy = gpu_uniform(gl, prec, s, dx, dy, h=h, G=2.5)
+    ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, h, G=2.5)
+    assert an.rel_l2((fx, fy), (ox, oy)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_headline_1024_sampled(gl, prec):
+    """The 1024^2 noisy spiral disk (2048^2 zero-padded FFT): sampled targets
+    against the oracle's full direct sum at those targets."""
+    n = 1024
+    s, dx, dy, h = diskgen.noisy_spiral(n, 0)
+    fx, fy = gpu_uniform(gl, prec, s, dx, dy, h=h)
+    rng = np.random.default_rng(2024)
+    tg = np.concatenate([rng.choice(n * n, 40, replace=False),
+                         [0, n - 1, n * n - 1, n * (n - 1), n * (n // 2) + n // 2]])
+    ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, h, targets=tg)
+    assert an.rel_l2((fx.ravel()[tg], fy.ravel()[tg]), (ox, oy)) < TOL[prec]
+
+
+def test_table1_row_512_on_gpu(gl):
+    """Table 1 row N_k = 256 (512^2 grid) from the GPU path: printed max norms
+    to three digits (a property of the exact discrete sum at this size)."""
+    n = 512
+    X, Y = diskgen.grid_centres(n)
+    s, dx, dy = diskgen.d2(X, Y)
+    fx, fy = gpu_uniform(gl, "f64", s, dx, dy)
+    ax, ay = an.d2_force(X, Y)
+    R = np.hypot(X, Y)
+    _, x2, xi = an.norms(fx - ax, (2.0 / n) ** 2)
+    _, _, ri = an.norms((fx * X + fy * Y) / R - (ax * X + ay * Y) / R, (2.0 / n) ** 2)
+    assert abs(xi - 1.93e-3) <= 0.006e-3
+    assert abs(ri - 1.99e-3) <= 0.006e-3
+    assert abs(2 * x2 - 2.44e-4) <= 0.006e-4
+
+
+def _amr_parity(gl, lay, s, dx, dy, prec, targets=None):
+    p = gl.Plan(lay.n0, _prec(gl, prec), slopes=True, x0=lay.x0, y0=lay.y0, h0=lay.h0,
+                nlevels=lay.nlevels, patches=lay.patches)
+    assert p.n_cells == lay.total()
+    assert p.n_leaves == lay.nleaves()
+    fx, fy = p.solve(_dev(s, prec), _dev(dx, prec), _dev(dy, prec))
+    torch.cuda.synchronize()
+    fx, fy = _host(fx), _host(fy)
+    mask = lay.leaf_mask()
+    assert np.all(fx[~mask] == 0) and np.all(fy[~mask] == 0)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    if targets is not None:
+        sel = targets
+    else:
+        sel = np.arange(len(idx))
+    ox, oy = oracle.direct(rect, s[idx], dx[idx], dy[idx], cent[sel])
+    area = (rect[sel, 1] - rect[sel, 0]) * (rect[sel, 3] - rect[sel, 2])
+    return an.rel_l2((fx[idx[sel]], fy[idx[sel]]), (ox, oy), area)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_amr_table10_layout(gl, prec):
+    """The paper's Appendix A layout (28 leaves on 3 levels) against the leaf
+    direct sum, with a random linear density per leaf."""
+    lay = diskgen.table10_layout()
+    rng = np.random.default_rng(1)
+    n = lay.total()
+    s, dx, dy = rng.random(n) + 0.2, rng.standard_normal(n), rng.standard_normal(n)
+    m = lay.leaf_mask()
+    s, dx, dy = np.where(m, s, 0), np.where(m, dx, 0), np.where(m, dy, 0)
+    assert _amr_parity(gl, lay, s, dx, dy, prec) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_amr_small_flagged(gl, prec):
+    """A flagged 3-level layout (base 32^2, 32x32 child patches) of the Kuzmin
+    plus clumps profile: every leaf against the leaf direct sum."""
+    lay, s, dx, dy = diskgen.amr_config(5, n0=32, nlevels=3, thresh=0.15, a=0.05)
+    assert lay.validate() and len(lay.patches) > 0
+    assert _amr_parity(gl, lay, s, dx, dy, prec) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_amr_config3_sampled(gl, prec):
+    """The 3-level AMR workload (base 256^2, finest lattice 1024^2): leaf
+    targets sampled on every level against the leaf direct sum."""
+    lay, s, dx, dy = diskgen.amr_config(0)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    size = rect[:, 1] - rect[:, 0]
+    rng = np.random.default_rng(9)
+    sel = []
+    for hv in np.unique(size):
+        cand = np.nonzero(size == hv)[0]
+        sel.extend(rng.choice(cand, min(12, len(cand)), replace=False))
+    sel = np.array(sorted(sel))
+    assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
+
+
+def test_batch_bitwise_equals_single(gl):
+    sizes = [64, 128, 64, 32]
+    plans, ins, outs, singles = [], [], [], []
+    for k, n in enumerate(sizes):
+        prec = "f32" if k % 2 else "f64"
+        p = gl.Plan(n, _prec(gl, prec))
+        s, dx, dy = diskgen.random_fields(n, 40 + k)
+        t = [_dev(a, prec) for a in (s, dx, dy)]
+        plans.append(p)
+        ins.append(t)
+        singles.append(p.solve(*t))
+        outs.append((torch.empty_like(t[0]), torch.empty_like(t[0])))
+    lay = diskgen.table10_layout()
+    pa = gl.Plan(lay.n0, gl.F64, x0=lay.x0, y0=lay.y0, h0=lay.h0, nlevels=3, patches=lay.patches)
+    rng = np.random.default_rng(3)
+    ta = [_dev(rng.random(lay.total()), "f64") for _ in range(3)]
+    plans.append(pa)
+    ins.append(ta)
+    singles.append(pa.solve(*ta))
+    outs.append((torch.empty_like(ta[0]), torch.empty_like(ta[0])))
+    ws = torch.empty(gl.batch_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    gl.solve_batch(plans, [t[0] for t in ins], [t[1] for t in ins], [t[2] for t in ins],
+                   [o[0] for o in outs], [o[1] for o in outs], ws)
+    torch.cuda.synchronize()
+    for (a, b), (c, d) in zip(outs, singles):
+        assert torch.equal(a, c) and torch.equal(b, d)
+
+
+def test_deterministic(gl):
+    n = 256
+    s, dx, dy, h = diskgen.noisy_spiral(n, 1)
+    a = gpu_uniform(gl, "f32", s, dx, dy, h=h)
+    b = gpu_uniform(gl, "f32", s, dx, dy, h=h)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_invalid_requests(gl):
+    with pytest.raises(gl.GravityError) as e:
+        gl.Plan(48, gl.F32)
+    assert e.value.status == gl.EUNSUPPORTED
+    with pytest.raises(gl.GravityError) as e:
+        gl.Plan(8192, gl.F32)
+    assert e.value.status == gl.EUNSUPPORTED
+    with pytest.raises(gl.GravityError) as e:
+        gl.Plan(32, gl.F32, nlevels=2, patches=[(1, 1, 0, 4, 4)])  # odd corner
+    assert e.value.status == gl.EINVAL
+    with pytest.raises(gl.GravityError) as e:
+        gl.Plan(32, gl.F32, nlevels=3, patches=[(2, 0, 0, 8, 8)])  # not nested
+    assert e.value.status == gl.EINVAL
+    p = gl.Plan(32, gl.F32)
+    s = torch.zeros(32 * 32, device="cuda")
+    with pytest.raises(gl.GravityError) as e:
+        p.solve(s, None, None)  # slopes missing
+    assert e.value.status == gl.EINVAL
