@@ -116,6 +116,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["f32", "f64"], default=None,
+                    help="time one precision only (profiling runs)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="instead of the solver, run --steps device copies of BYTES bytes "
+                         "(reference kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X "
@@ -127,8 +132,22 @@ def main():
     import diskgen
     import paper_2001_02765_amd as gl
 
+    if args.copy_calib:
+        src = torch.ones(args.copy_calib // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": args.copy_calib, "copies": args.steps}), flush=True)
+        return
+
     n = args.n
     fields = diskgen.noisy_spiral(n, 0)
+    if args.only:
+        prec = gl.F32 if args.only == "f32" else gl.F64
+        r = run_precision(gl, torch, prec, n, args.steps, args.warmup, fields)
+        print(json.dumps({"only": args.only, "n": n, **r}), flush=True)
+        return
     r32 = run_precision(gl, torch, gl.F32, n, args.steps, args.warmup, fields)
     r64 = run_precision(gl, torch, gl.F64, n, args.steps, args.warmup, fields)
 

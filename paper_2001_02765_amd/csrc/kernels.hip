@@ -22,6 +22,7 @@ namespace grav {
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
 
 // Row transforms: length L = M/2 complex (two real samples packed per
 // element), E elements per thread, RPB rows per block.  Lanes are
@@ -34,7 +35,9 @@ template <typename T, int M> struct RowCfg {
     static constexpr int RMAX = sizeof(T) == 4 ? 8 : 4;
     static constexpr int REG = lds_region<L>();
     static constexpr int BYTES = REG * (int)sizeof(C<T>);
-    static constexpr int RPB = cmax(1, cmin(RMAX, cmin(1024 / NTR, 65536 / BYTES)));
+    // a power of two (rows per solve are powers of two), LDS kept <= 80 KB
+    static constexpr int RPB = floor_pow2(cmax(1, cmin(RMAX, cmin(1024 / NTR, 81920 / BYTES))));
+    static_assert((RPB & (RPB - 1)) == 0, "rows per block must be a power of two");
     static constexpr int NTH = RPB * NTR;
 };
 
@@ -407,6 +410,7 @@ template <typename T, int M> struct Dispatch {
     static hipError_t row_fwd(const RowFwdArgs<T> &a, bool pruned, int nrows, int nfields,
                               const C<T> *tw, hipStream_t s) {
         using CF = RowCfg<T, M>;
+        if (nrows % CF::RPB) return hipErrorInvalidValue;
         dim3 grid(nrows / CF::RPB, nfields);
         if (pruned)
             hipLaunchKernelGGL((k_row_fwd<T, M, true>), grid, dim3(CF::NTH), 0, s, a, tw);
@@ -433,6 +437,7 @@ template <typename T, int M> struct Dispatch {
     static hipError_t row_inv(const RowInvArgs<T> &a, int nrows, int nout, const C<T> *tw,
                               hipStream_t s) {
         using CF = RowCfg<T, M>;
+        if (nrows % CF::RPB) return hipErrorInvalidValue;
         dim3 grid(nrows / CF::RPB, nout);
         hipLaunchKernelGGL((k_row_inv<T, M>), grid, dim3(CF::NTH), 0, s, a, tw);
         return hipGetLastError();

@@ -133,6 +133,26 @@ def test_headline_1024_sampled(gl, prec):
     assert an.rel_l2((fx.ravel()[tg], fy.ravel()[tg]), (ox, oy)) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_largest_sizes_sampled(gl, prec, n):
+    """The two largest supported lattices (FFT sizes 4096 and 8192): sampled
+    targets, including the four corner cells, against the oracle's per-pair
+    direct sum over every source cell."""
+    X, Y = diskgen.grid_centres(n)
+    s, dx, dy = diskgen.spiral(X, Y, "kuzmin", 0.3, 0.15, 20.0, 1.0)
+    fx, fy = gpu_uniform(gl, prec, s, dx, dy)
+    rng = np.random.default_rng(n)
+    tg = np.concatenate([rng.choice(n * n, 8, replace=False), [0, n - 1, n * n - 1, n * (n - 1)]])
+    h = 2.0 / n
+    e = -1.0 + h * np.arange(n)
+    EX, EY = np.meshgrid(e, e)
+    rect = np.stack([EX.ravel(), EX.ravel() + h, EY.ravel(), EY.ravel() + h], 1)
+    cent = np.stack([X.ravel(), Y.ravel()], 1)
+    ox, oy = oracle.direct(rect, s.ravel(), dx.ravel(), dy.ravel(), cent[tg])
+    assert an.rel_l2((fx.ravel()[tg], fy.ravel()[tg]), (ox, oy)) < TOL[prec]
+
+
 def test_table1_row_512_on_gpu(gl):
     """Table 1 row N_k = 256 (512^2 grid) from the GPU path: printed max norms
     to three digits (a property of the exact discrete sum at this size)."""
