@@ -93,6 +93,7 @@ typedef struct {
     int64_t n_leaves;    /* leaf zones (forces computed) */
     size_t workspace_bytes;
     size_t resident_bytes; /* device memory held by the plan and its spectra */
+    int32_t variants[3];   /* kernel variants in use (row forward, column, row inverse) */
 } gravity_plan_info_t;
 
 /*
@@ -102,6 +103,10 @@ typedef struct {
  * K^{x,y} and the y family) at every source offset, built in double
  * precision on the device and transformed with a double precision FFT.
  * Sizes: 16 <= n_finest <= 4096, powers of two.
+ * Kernel variants: unless GRAVITY_AUTOTUNE=0, the first plan of each size,
+ * precision and layout kind times every variant of its three FFT kernels
+ * and keeps the fastest (GRAVITY_TUNE_FILE persists the choices,
+ * GRAVITY_VARIANTS="rf,col,ri" forces them).
  * Errors: EINVAL (bad descriptor or nesting), EUNSUPPORTED (size or
  * non-square grid), ENOMEM, EDEVICE.  *out is NULL on error.
  * Runs on the calling thread's current HIP device, which the plan records;

@@ -47,7 +47,8 @@ class DescT(ctypes.Structure):
 class InfoT(ctypes.Structure):
     _fields_ = [("n_finest", ctypes.c_int32), ("fft_size", ctypes.c_int32),
                 ("n_cells", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t),
+                ("variants", ctypes.c_int32 * 3)]
 
 
 _vp = ctypes.c_void_p
@@ -138,6 +139,7 @@ class Plan:
         self.n_leaves = info.n_leaves
         self.workspace_bytes = info.workspace_bytes
         self.resident_bytes = info.resident_bytes
+        self.variants = tuple(info.variants)
 
     @property
     def handle(self):

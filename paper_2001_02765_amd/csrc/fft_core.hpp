@@ -207,3 +207,118 @@ __device__ __forceinline__ void fft(C<T> *reg, C<T> *lds, const C<T> *__restrict
 }
 
 }  // namespace grav
+
+namespace grav {
+
+// ---------------------------------------------------------------------------
+// Register-twiddle variant.  A thread's twiddles depend only on its index and
+// the pass, not on the data, so a kernel that runs several transforms of the
+// same length (the column kernel runs five) loads them once into registers
+// (TwReg) and every pass of every transform, forward or inverse, reuses them.
+// fft_multi runs NB independent transforms in lockstep (shared twiddles, NB
+// LDS regions lds + i * ldss).
+// ---------------------------------------------------------------------------
+
+template <int L, int NT, int P> struct PassInfo {
+    using PL = Plan<L, NT>;
+    using PREV = PassInfo<L, NT, P - 1>;
+    static constexpr int R = PL::radix(P);
+    static constexpr int E = PL::E;
+    static constexpr int B = E / R;
+    static constexpr int NS = PREV::NS * PREV::R;
+};
+template <int L, int NT> struct PassInfo<L, NT, 0> {
+    using PL = Plan<L, NT>;
+    static constexpr int R = PL::radix(0);
+    static constexpr int E = PL::E;
+    static constexpr int B = E / R;
+    static constexpr int NS = 1;
+};
+
+// number of complex twiddle registers needed by passes [P, npass)
+template <int L, int NT, int P> constexpr int tw_count() {
+    if constexpr (P >= Plan<L, NT>::npass) return 0;
+    else {
+        using PI = PassInfo<L, NT, P>;
+        return (PI::NS > 1 ? PI::B * (PI::R - 1) : 0) + tw_count<L, NT, P + 1>();
+    }
+}
+
+template <typename T, int L, int NT> struct TwReg {
+    static constexpr int N = tw_count<L, NT, 0>() > 0 ? tw_count<L, NT, 0>() : 1;
+    C<T> w[N];
+
+    template <int P, int OFF>
+    __device__ __forceinline__ void load_pass(const C<T> *__restrict__ tw, int tws, int t) {
+        if constexpr (P < Plan<L, NT>::npass) {
+            using PI = PassInfo<L, NT, P>;
+            constexpr int NS = PI::NS, R = PI::R, B = PI::B;
+            constexpr int CNT = (NS > 1) ? B * (R - 1) : 0;
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int k = (t + NT * b) & (NS - 1);
+#pragma unroll
+                    for (int r = 1; r < R; ++r)
+                        w[OFF + b * (R - 1) + (r - 1)] = tw[(r * k * (L / (NS * R))) * tws];
+                }
+            }
+            load_pass<P + 1, OFF + CNT>(tw, tws, t);
+        }
+    }
+    __device__ __forceinline__ void load(const C<T> *__restrict__ tw, int tws, int t) {
+        load_pass<0, 0>(tw, tws, t);
+    }
+};
+
+template <typename T, int L, int NT, int DIR, int NB, int P, int OFF>
+__device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, int ldss, const TwReg<T, L, NT> &tr,
+                                      int t) {
+    using PI = PassInfo<L, NT, P>;
+    constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
+    constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
+    constexpr int CNT = (NS > 1) ? B * (R - 1) : 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + NT * b;
+        const int k = j & (NS - 1);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            C<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = reg[i][b + r * B];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[r] = twm<DIR, T>(v[r], tr.w[OFF + b * (R - 1) + (r - 1)]);
+            }
+            dft<R, DIR, T>(v);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) reg[i][b + r * B] = v[r];
+            } else {
+                const int base = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[i * ldss + pidx(base + r * NS)] = v[r];
+            }
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int e = 0; e < E; ++e) reg[i][e] = lds[i * ldss + pidx(t + NT * e)];
+        __syncthreads();
+        mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT>(reg, lds, ldss, tr, t);
+    }
+}
+
+// NB length-L transforms in lockstep; reg[i][e] holds element t + NT e of
+// transform i on entry and exit.
+template <typename T, int L, int NT, int DIR, int NB>
+__device__ __forceinline__ void fft_multi(C<T> (*reg)[L / NT], C<T> *lds, int ldss,
+                                          const TwReg<T, L, NT> &tr, int t) {
+    mpass<T, L, NT, DIR, NB, 0, 0>(reg, lds, ldss, tr, t);
+}
+
+}  // namespace grav

@@ -210,7 +210,7 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
         ra.out = (C<double> *)rows.p;
         ra.out_pitch = M;
         ra.out_fstride = 0;
-        hip_check(launch_row_fwd<double>(ra, M, false, M, 1, (const C<double> *)tw64->tw.p, s),
+        hip_check(launch_row_fwd<double>(ra, M, 0, false, M, 1, (const C<double> *)tw64->tw.p, s),
                   "kernel table row transform");
         const int imag = (kind == 0 || kind == 3) ? 1 : 0;
         if (prec) {
@@ -264,6 +264,8 @@ struct gravity_plan_s {
     std::shared_ptr<Twiddles> tw;
     std::shared_ptr<KernelSet> centre, corner;
     DevBuf owner, gmap;
+    // kernel variants (row forward, column, row inverse), chosen at plan time
+    int var_rf = 0, var_col = 0, var_ri = 0;
     // workspace layout (byte offsets)
     size_t off_w = 0, off_a = 0, off_b = 0, off_o = 0, ws_bytes = 0;
 };
@@ -433,7 +435,7 @@ void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const 
     ra.out_pitch = n;
     ra.out_fstride = colsz;
     mark();
-    hip_check(launch_row_fwd<T>(ra, M, true, n, NF, tw, s), "row transform");
+    hip_check(launch_row_fwd<T>(ra, M, p.var_rf, true, n, NF, tw, s), "row transform");
 
     ColArgs<T> ca{};
     ca.in = A;
@@ -448,7 +450,7 @@ void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const 
     ca.out_gstride = colsz;
     const int nfam = p.amr ? 2 : 1;
     mark();
-    hip_check(launch_col<T>(ca, M, NF, nfam, tw, ph, s), "column transform");
+    hip_check(launch_col<T>(ca, M, p.var_col, NF, nfam, tw, ph, s), "column transform");
 
     RowInvArgs<T> ia{};
     ia.in = B;
@@ -460,14 +462,14 @@ void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const 
         ia.out[0] = (T *)fx;
         ia.out[1] = (T *)fy;
         mark();
-        hip_check(launch_row_inv<T>(ia, M, n, 2, tw, s), "inverse row transform");
+        hip_check(launch_row_inv<T>(ia, M, p.var_ri, n, 2, tw, s), "inverse row transform");
         mark();
     } else {
         T *O = (T *)(ws + p.off_o);
         const int64_t n2 = (int64_t)n * n;
         for (int g = 0; g < 4; ++g) ia.out[g] = O + g * n2;
         mark();
-        hip_check(launch_row_inv<T>(ia, M, n, 4, tw, s), "inverse row transform");
+        hip_check(launch_row_inv<T>(ia, M, p.var_ri, n, 4, tw, s), "inverse row transform");
         GatherArgs<T> ga{};
         ga.gmap = (const int32_t *)p.gmap.p;
         for (int g = 0; g < 4; ++g) ga.o[g] = O + g * n2;
@@ -478,6 +480,140 @@ void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const 
         hip_check(launch_gather<T>(ga, s), "gather");
         mark();
     }
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: per (device, M, precision, fields, families) pick the fastest
+// variant of each solve kernel by timing all of them on scratch buffers.
+// GRAVITY_AUTOTUNE=0 keeps the defaults; GRAVITY_VARIANTS="rf,col,ri" forces
+// a choice; GRAVITY_TUNE_FILE names a text file that persists choices.
+// ---------------------------------------------------------------------------
+struct Variants {
+    int rf, col, ri;
+};
+std::map<std::tuple<std::string, int, int, int, int>, Variants> g_tuned;
+bool g_tune_file_loaded = false;
+
+std::string device_key(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string s = prop.gcnArchName;
+    for (auto &c : s)
+        if (c == ' ') c = '_';
+    return s + "/" + std::to_string(prop.multiProcessorCount);
+}
+
+void load_tune_file() {
+    if (g_tune_file_loaded) return;
+    g_tune_file_loaded = true;
+    const char *path = std::getenv("GRAVITY_TUNE_FILE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char dev[256];
+    int M, prec, nf, nfam, rf, col, ri;
+    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d", dev, &M, &prec, &nf, &nfam, &rf, &col, &ri) == 8)
+        g_tuned[std::make_tuple(std::string(dev), M, prec, nf, nfam)] = Variants{rf, col, ri};
+    std::fclose(f);
+}
+
+void save_tune_entry(const std::string &dev, int M, int prec, int nf, int nfam, const Variants &v) {
+    const char *path = std::getenv("GRAVITY_TUNE_FILE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", dev.c_str(), M, prec, nf, nfam, v.rf, v.col, v.ri);
+    std::fclose(f);
+}
+
+bool col_ok(const gravity_plan_s &p, int v) {
+    return col_variant_valid(p.prec, p.M, v, p.nfields, p.amr ? 2 : 1);
+}
+
+Variants default_variants(const gravity_plan_s &p) {
+    Variants v{1, 0, 1};
+    if (!row_variant_valid(p.M, v.rf)) v.rf = 0;
+    if (!row_variant_valid(p.M, v.ri)) v.ri = 0;
+    if (!col_ok(p, v.col)) v.col = 0;
+    return v;
+}
+
+template <typename T> Variants autotune(gravity_plan_s &p) {
+    const int M = p.M;
+    const int ns = n_stages(p);
+    const int s_rf = p.amr ? 1 : 0, s_col = p.amr ? 2 : 1, s_ri = p.amr ? 3 : 2;
+    DevBuf ws(p.ws_bytes, "autotune workspace");
+    DevBuf in(3 * sizeof(T) * (size_t)p.ncells, "autotune inputs");
+    DevBuf out(2 * sizeof(T) * (size_t)p.ncells, "autotune outputs");
+    hip_check(hipMemset(in.p, 0, in.bytes), "autotune memset");
+    const T *sg = (const T *)in.p;
+    std::vector<hipEvent_t> ev(ns + 1, nullptr);
+    Variants best = default_variants(p);
+    struct EvGuard {
+        std::vector<hipEvent_t> &e;
+        ~EvGuard() {
+            for (auto x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } guard{ev};
+    for (auto &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    double tb[3] = {1e300, 1e300, 1e300};
+    const int reps = M >= 4096 ? 3 : 8;
+    for (int v = 0; v < kNumVariants; ++v) {
+        const bool okr = row_variant_valid(M, v), okc = col_ok(p, v);
+        if (!okr && !okc) continue;
+        p.var_rf = okr ? v : best.rf;
+        p.var_ri = okr ? v : best.ri;
+        p.var_col = okc ? v : best.col;
+        double acc[8] = {0};
+        for (int r = 0; r <= reps; ++r) {
+            solve_t<T>(p, sg, sg + p.ncells, sg + 2 * p.ncells, out.p, (T *)out.p + p.ncells,
+                       (char *)ws.p, nullptr, ev.data());
+            hip_check(hipEventSynchronize(ev[ns]), "hipEventSynchronize");
+            if (r == 0) continue;  // warm-up
+            for (int k = 0; k < ns; ++k) {
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
+                acc[k] += ms;
+            }
+        }
+        if (okr && acc[s_rf] < tb[0]) { tb[0] = acc[s_rf]; best.rf = v; }
+        if (okc && acc[s_col] < tb[1]) { tb[1] = acc[s_col]; best.col = v; }
+        if (okr && acc[s_ri] < tb[2]) { tb[2] = acc[s_ri]; best.ri = v; }
+    }
+    return best;
+}
+
+void choose_variants(gravity_plan_s &p) {
+    const char *force = std::getenv("GRAVITY_VARIANTS");
+    if (force && *force) {
+        int a = 0, b = 0, c = 0;
+        if (std::sscanf(force, "%d,%d,%d", &a, &b, &c) != 3 || !row_variant_valid(p.M, a) ||
+            !col_ok(p, b) || !row_variant_valid(p.M, c))
+            fail(GRAVITY_EINVAL, "GRAVITY_VARIANTS must be three valid variant ids 'rf,col,ri'");
+        p.var_rf = a;
+        p.var_col = b;
+        p.var_ri = c;
+        return;
+    }
+    Variants v = default_variants(p);
+    const char *at = std::getenv("GRAVITY_AUTOTUNE");
+    if (!(at && std::string(at) == "0")) {
+        load_tune_file();
+        const std::string dev = device_key(p.device);
+        auto key = std::make_tuple(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            v = it->second;
+        } else {
+            v = p.prec ? autotune<double>(p) : autotune<float>(p);
+            g_tuned[key] = v;
+            save_tune_entry(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1, v);
+        }
+    }
+    p.var_rf = v.rf;
+    p.var_col = v.col;
+    p.var_ri = v.ri;
 }
 
 }  // namespace
@@ -553,6 +689,10 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
             off += align256(esz * 4 * (size_t)(n * n));
         }
         p->ws_bytes = off;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            choose_variants(*p);
+        }
         *out = p.release();
     });
 }
@@ -577,6 +717,9 @@ gravity_status_t gravity_plan_get_info(gravity_plan_t p, gravity_plan_info_t *in
         if (p->corner) r += p->corner->q.bytes;
         if (p->tw) r += p->tw->tw.bytes + p->tw->ph.bytes;
         info->resident_bytes = r;
+        info->variants[0] = p->var_rf;
+        info->variants[1] = p->var_col;
+        info->variants[2] = p->var_ri;
     });
 }
 

@@ -68,20 +68,22 @@ struct TableArgs {
     double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]
 };
 
-// Launch configurations (threads per block) used by the launchers.
-int row_threads(int prec, int M);
-int row_rows_per_block(int prec, int M);
-int col_threads(int prec, int M);
+// Kernel variants of the three solve kernels (see kernels_impl.hpp):
+// bit 1 selects 16 elements per thread (else 8), bit 0 selects all fields
+// per thread.  kNumVariants variants exist for each kernel and size.
+constexpr int kNumVariants = 4;
+bool row_variant_valid(int M, int var);
+bool col_variant_valid(int prec, int M, int var, int nfields, int nfam);
 
 template <typename T>
-hipError_t launch_row_fwd(const RowFwdArgs<T> &a, int M, bool pruned, int nrows, int nfields,
-                          const C<T> *tw, hipStream_t s);
+hipError_t launch_row_fwd(const RowFwdArgs<T> &a, int M, int var, bool pruned, int nrows,
+                          int nfields, const C<T> *tw, hipStream_t s);
 template <typename T>
-hipError_t launch_col(const ColArgs<T> &a, int M, int nfields, int nfam, const C<T> *tw,
+hipError_t launch_col(const ColArgs<T> &a, int M, int var, int nfields, int nfam, const C<T> *tw,
                       const C<T> *ph, hipStream_t s);
 template <typename T>
-hipError_t launch_row_inv(const RowInvArgs<T> &a, int M, int nrows, int nout, const C<T> *tw,
-                          hipStream_t s);
+hipError_t launch_row_inv(const RowInvArgs<T> &a, int M, int var, int nrows, int nout,
+                          const C<T> *tw, hipStream_t s);
 template <typename T> hipError_t launch_inject(const InjectArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_gather(const GatherArgs<T> &a, hipStream_t s);
 

@@ -1,0 +1,298 @@
+// Auxiliary kernels: kernel tables and their spectra (plan time), AMR
+// injection and gather.
+//
+//  k_ktable      exact cell-integrated kernels at every source offset (FP64)
+//  k_col_extract forward column transform of a table's row spectra and
+//                storage of one real quadrant
+//  k_inject      AMR: composite leaves -> finest lattice (linear density)
+//  k_gather      AMR: finest-lattice forces -> composite leaf outputs
+#include "kernels_impl.hpp"
+
+#include <cmath>
+
+namespace grav {
+
+// Column transforms of the table spectra: length M, 8 elements per thread.
+template <int M> struct ExtractCfg {
+    static constexpr int E = 8;
+    static constexpr int NT = M / E;
+};
+
+// ---------------------------------------------------------------------------
+// kernel tables (double precision, cell units)
+// ---------------------------------------------------------------------------
+
+// ln(a + sqrt(a^2 + b^2)); b == 0 uses the x-bar = x convention sgn(a) ln|a|;
+// a < 0 uses ln(b^2 / (R - a)) (no cancellation).
+__device__ double lam(double a, double b) {
+    if (b == 0.0) return a > 0.0 ? log(a) : -log(-a);
+    const double R = sqrt(a * a + b * b);
+    if (a >= 0.0) return log(a + R);
+    return log((b * b) / (R - a));
+}
+__device__ double vlam(double v, double u) { return v == 0.0 ? 0.0 : v * lam(u, v); }
+__device__ double rad(double u, double v) { return sqrt(u * u + v * v); }
+
+// Exact kernel `kind` of the unit source cell [u1,u2] x [v1,v2] (offsets
+// from the target) whose centre is (uc, vc); t0zero: the target touches the
+// cell at a corner, where K^{x,0} and K^{y,0} are replaced by 0 (their
+// divergent parts cancel against the adjacent cells of the same zone).
+__device__ double closed_kernel(int kind, double uc, double vc, bool t0zero) {
+    const double u1 = uc - 0.5, u2 = uc + 0.5, v1 = vc - 0.5, v2 = vc + 0.5;
+    const double dxc = -uc, dyc = -vc;  // x_t - x_c, y_t - y_c
+    if (kind < 3) {
+        double k0 = 0.0;
+        if (!t0zero) k0 = -((lam(v2, u2) - lam(v2, u1)) - (lam(v1, u2) - lam(v1, u1)));
+        if (kind == 0) return k0;
+        if (kind == 1) return dxc * k0 + ((vlam(v2, u2) - vlam(v2, u1)) - (vlam(v1, u2) - vlam(v1, u1)));
+        return dyc * k0 - ((rad(u2, v2) - rad(u1, v2)) - (rad(u2, v1) - rad(u1, v1)));
+    } else {
+        double k0 = 0.0;
+        if (!t0zero) k0 = -((lam(u2, v2) - lam(u2, v1)) - (lam(u1, v2) - lam(u1, v1)));
+        if (kind == 3) return k0;
+        if (kind == 4) return dxc * k0 - ((rad(v2, u2) - rad(v1, u2)) - (rad(v2, u1) - rad(v1, u1)));
+        return dyc * k0 + ((vlam(u2, v2) - vlam(u2, v1)) - (vlam(u1, v2) - vlam(u1, v1)));
+    }
+}
+
+// The same integral by a 10 x 10 Gauss-Legendre rule, used for cells at
+// least 3.5 cells from the target: there the integrand is analytic in a
+// Bernstein ellipse of parameter >= 15 about the cell, so the rule's error
+// is below 1e-23 relative, while the closed form's double difference would
+// cancel ~2 log10(distance) digits.
+__device__ double quad_kernel(int kind, double uc, double vc, const TableArgs &a) {
+    double sum = 0.0;
+    for (int i = 0; i < 10; ++i) {
+        const double du = 0.5 * a.glx[i];
+        const double u = uc + du;
+        double si = 0.0;
+        for (int jj = 0; jj < 10; ++jj) {
+            const double dv = 0.5 * a.glx[jj];
+            const double v = vc + dv;
+            const double r2 = u * u + v * v;
+            const double ir = 1.0 / sqrt(r2);
+            const double ir3 = ir * ir * ir;
+            double f;
+            switch (kind) {
+                case 0: f = u; break;
+                case 1: f = du * u; break;
+                case 2: f = dv * u; break;
+                case 3: f = v; break;
+                case 4: f = du * v; break;
+                default: f = dv * v; break;
+            }
+            si += a.glw[jj] * f * ir3;
+        }
+        sum += a.glw[i] * si;
+    }
+    return 0.25 * sum;
+}
+
+// Circulant table c[m] = K(-m): entry (my, mx) holds the kernel of the source
+// cell at offset d = -(signed m) from the target.  Family 0 (cell-centre
+// targets): cell [d - 1/2, d + 1/2], |d| <= M/2 - 1, the rest zero.
+// Family 1 (targets on lattice corners): cell [d, d + 1], d in [-M/2, M/2 - 1].
+__global__ void __launch_bounds__(256) k_ktable(TableArgs a) {
+    const int64_t total = (int64_t)a.M * a.M;
+    const int H = a.M / 2;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int mx = (int)(q % a.M), my = (int)(q / a.M);
+        double val = 0.0;
+        int sx, sy;
+        if (a.family == 0) {
+            sx = mx < H ? mx : mx - a.M;
+            sy = my < H ? my : my - a.M;
+        } else {
+            sx = mx <= H ? mx : mx - a.M;
+            sy = my <= H ? my : my - a.M;
+        }
+        const int dx = -sx, dy = -sy;
+        bool valid = true;
+        if (a.family == 0) valid = (mx != H) && (my != H);
+        if (valid) {
+            const double off = a.family == 0 ? 0.0 : 0.5;
+            const double uc = dx + off, vc = dy + off;
+            const double distx = fmax(fabs(uc) - 0.5, 0.0), disty = fmax(fabs(vc) - 0.5, 0.0);
+            if (fmax(distx, disty) >= 3.5) {
+                val = quad_kernel(a.kind, uc, vc, a);
+            } else {
+                const bool t0zero = a.family == 1 && (dx == 0 || dx == -1) && (dy == 0 || dy == -1);
+                val = closed_kernel(a.kind, uc, vc, t0zero);
+            }
+        }
+        a.out[q] = val;
+    }
+}
+
+template <typename TQ, int M>
+__global__ void __launch_bounds__((ExtractCfg<M>::NT))
+    k_col_extract(const C<double> *__restrict__ in, TQ *__restrict__ q, int64_t q_pitch, int imag,
+                  int corner, const C<double> *__restrict__ tw, const C<double> *__restrict__ ph) {
+    constexpr int E = ExtractCfg<M>::E, NT = ExtractCfg<M>::NT, H = M / 2;
+    __shared__ C<double> lds[lds_region<M>()];
+    const int t = threadIdx.x;
+    const int kx = blockIdx.x;
+    const C<double> *src = in + (int64_t)kx * M;
+    C<double> reg[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) reg[e] = src[t + NT * e];
+    fft<double, M, NT, -1>(reg, lds, tw, 1, t);
+    TQ *dst = q + (int64_t)kx * q_pitch;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int ky = t + NT * e;
+        if (ky <= H) {
+            C<double> v = reg[e];
+            if (corner) v = cmulc<double>(v, cmul<double>(ph[kx], ph[ky]));
+            dst[ky] = (TQ)(imag ? v.y : v.x);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// AMR injection and gather
+// ---------------------------------------------------------------------------
+template <typename T> __global__ void __launch_bounds__(256) k_inject(InjectArgs<T> a) {
+    const int64_t n2 = (int64_t)a.nf * a.nf;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n2) return;
+    const int I = (int)(idx % a.nf), J = (int)(idx / a.nf);
+    const int32_t o = a.owner[idx];
+    const int32_t c = o & 0x0FFFFFFF;
+    const int kb = (o >> 28) & 0xF;
+    const int B = 1 << kb;
+    T s = a.s[c];
+    T dx = 0, dy = 0;
+    if (a.slopes) {
+        dx = a.dx[c];
+        dy = a.dy[c];
+        // offset of this finest cell's centre from the leaf centre
+        const T ox = (T)(2 * (I & (B - 1)) + 1 - B) * (T)0.5 * a.hf;
+        const T oy = (T)(2 * (J & (B - 1)) + 1 - B) * (T)0.5 * a.hf;
+        s = s + dx * ox + dy * oy;
+    }
+    a.w0[idx] = s;
+    if (a.slopes) {
+        a.w1[idx] = dx;
+        a.w2[idx] = dy;
+    }
+}
+
+template <typename T> __global__ void __launch_bounds__(256) k_gather(GatherArgs<T> a) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    const int32_t m = a.gmap[c];
+    if (m < 0) {
+        a.fx[c] = 0;
+        a.fy[c] = 0;
+        return;
+    }
+    const int fam = (m >> 30) & 1;
+    const int32_t pos = m & 0x3FFFFFFF;
+    a.fx[c] = a.o[2 * fam][pos];
+    a.fy[c] = a.o[2 * fam + 1][pos];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+template <typename TQ, int M>
+static hipError_t col_extract_m(const C<double> *in, TQ *q, int64_t q_pitch, int imag, int corner,
+                                const C<double> *tw, const C<double> *ph, hipStream_t s) {
+    hipLaunchKernelGGL((k_col_extract<TQ, M>), dim3(M / 2 + 1), dim3(ExtractCfg<M>::NT), 0, s, in, q,
+                       q_pitch, imag, corner, tw, ph);
+    return hipGetLastError();
+}
+
+template <int M> static bool row_ok(int var) {
+    switch (var) {
+        case 0: return row_var_ok<M, 0>();
+        case 1: return row_var_ok<M, 1>();
+        case 2: return row_var_ok<M, 2>();
+        case 3: return row_var_ok<M, 3>();
+    }
+    return false;
+}
+template <typename T, int M, int NF, int NFAM> static bool col_ok(int var) {
+    switch (var) {
+        case 0: return col_var_ok<T, M, 0, NF, NFAM>();
+        case 1: return col_var_ok<T, M, 1, NF, NFAM>();
+        case 2: return col_var_ok<T, M, 2, NF, NFAM>();
+        case 3: return col_var_ok<T, M, 3, NF, NFAM>();
+    }
+    return false;
+}
+template <typename T, int M> static bool col_ok_k(int var, int nf, int nfam) {
+    if (nf == 3 && nfam == 1) return col_ok<T, M, 3, 1>(var);
+    if (nf == 3 && nfam == 2) return col_ok<T, M, 3, 2>(var);
+    if (nf == 1 && nfam == 1) return col_ok<T, M, 1, 1>(var);
+    if (nf == 1 && nfam == 2) return col_ok<T, M, 1, 2>(var);
+    return false;
+}
+template <int M> static bool col_ok_p(int prec, int var, int nf, int nfam) {
+    return prec ? col_ok_k<double, M>(var, nf, nfam) : col_ok_k<float, M>(var, nf, nfam);
+}
+bool row_variant_valid(int M, int var) {
+    switch (M) {
+        case 32: return row_ok<32>(var);
+        case 64: return row_ok<64>(var);
+        case 128: return row_ok<128>(var);
+        case 256: return row_ok<256>(var);
+        case 512: return row_ok<512>(var);
+        case 1024: return row_ok<1024>(var);
+        case 2048: return row_ok<2048>(var);
+        case 4096: return row_ok<4096>(var);
+        case 8192: return row_ok<8192>(var);
+    }
+    return false;
+}
+bool col_variant_valid(int prec, int M, int var, int nf, int nfam) {
+    switch (M) {
+        case 32: return col_ok_p<32>(prec, var, nf, nfam);
+        case 64: return col_ok_p<64>(prec, var, nf, nfam);
+        case 128: return col_ok_p<128>(prec, var, nf, nfam);
+        case 256: return col_ok_p<256>(prec, var, nf, nfam);
+        case 512: return col_ok_p<512>(prec, var, nf, nfam);
+        case 1024: return col_ok_p<1024>(prec, var, nf, nfam);
+        case 2048: return col_ok_p<2048>(prec, var, nf, nfam);
+        case 4096: return col_ok_p<4096>(prec, var, nf, nfam);
+        case 8192: return col_ok_p<8192>(prec, var, nf, nfam);
+    }
+    return false;
+}
+
+template <typename T> hipError_t launch_inject(const InjectArgs<T> &a, hipStream_t s) {
+    const int64_t n2 = (int64_t)a.nf * a.nf;
+    hipLaunchKernelGGL((k_inject<T>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_gather(const GatherArgs<T> &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_ktable(const TableArgs &a, hipStream_t s) {
+    const int64_t total = (int64_t)a.M * a.M;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_ktable, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename TQ>
+hipError_t launch_col_extract(const C<double> *in, int M, TQ *q, int64_t q_pitch, int imag,
+                              int corner, const C<double> *tw, const C<double> *ph,
+                              hipStream_t s) {
+    GRAV_SWITCH_M(M, return (col_extract_m<TQ, MM>(in, q, q_pitch, imag, corner, tw, ph, s)))
+}
+
+template hipError_t launch_inject<float>(const InjectArgs<float> &, hipStream_t);
+template hipError_t launch_inject<double>(const InjectArgs<double> &, hipStream_t);
+template hipError_t launch_gather<float>(const GatherArgs<float> &, hipStream_t);
+template hipError_t launch_gather<double>(const GatherArgs<double> &, hipStream_t);
+template hipError_t launch_col_extract<float>(const C<double> *, int, float *, int64_t, int, int,
+                                              const C<double> *, const C<double> *, hipStream_t);
+template hipError_t launch_col_extract<double>(const C<double> *, int, double *, int64_t, int, int,
+                                               const C<double> *, const C<double> *, hipStream_t);
+
+}  // namespace grav

@@ -1,0 +1,407 @@
+// Solve-path kernels (templates) and their launch dispatch.  Instantiated per
+// precision in kernels_f32.hip / kernels_f64.hip.
+//
+//  k_row_fwd   real-to-complex row transforms of zero-padded fields,
+//              written transposed (column-major spectra)
+//  k_col       per spectral column: forward column transforms of the input
+//              fields, products with the kernel spectra, inverse column
+//              transforms of the force components
+//  k_row_inv   complex-to-real row transforms of the force components
+//
+// Each kernel has variants (elements per thread E, and how many transforms a
+// thread carries: one field per block row, or all fields in sequence or in
+// lockstep); the plan's autotuner times them and keeps the fastest.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace grav {
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
+
+// Row transforms: length L = M/2 complex (two real samples packed per
+// element), E elements per thread, RPB rows per block.  Lanes are
+// interleaved with the row index fastest, so one store instruction writes
+// RPB consecutive rows of a spectral column (transposed, coalesced output).
+template <typename T, int M, int E> struct RowCfg {
+    static constexpr int L = M / 2;
+    static constexpr int NTR = L / E;
+    static constexpr int RMAX = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int REG = lds_region<L>();
+    static constexpr int BYTES = REG * (int)sizeof(C<T>);
+    // a power of two (rows per solve are powers of two), LDS kept <= 80 KB
+    static constexpr int RPB = floor_pow2(cmax(1, cmin(RMAX, cmin(1024 / NTR, 81920 / BYTES))));
+    static constexpr int NTH = RPB * NTR;
+    static_assert((RPB & (RPB - 1)) == 0, "rows per block must be a power of two");
+};
+
+// variant ids: bit 1 selects E = 16 (else 8); bit 0 selects all fields per
+// thread (rows: in sequence; columns: in lockstep) instead of one.
+constexpr int var_e(int v) { return (v & 2) ? 16 : 8; }
+constexpr bool var_all(int v) { return (v & 1) != 0; }
+template <int M, int V> constexpr bool row_var_ok() { return M / 2 >= 2 * var_e(V); }
+template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok();
+
+// ---------------------------------------------------------------------------
+// row forward: z[m] = x[2m] + i x[2m+1] -> Z = FFT_L(z) -> X[k], k in [0, L]
+// ---------------------------------------------------------------------------
+template <typename T, int M, int V, bool PRUNED>
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
+    k_row_fwd(RowFwdArgs<T> a, int nfields, const C<T> *__restrict__ tw) {
+    constexpr int E = var_e(V);
+    using CF = RowCfg<T, M, E>;
+    constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
+    __shared__ C<T> lds[RPB * CF::REG];
+    const int t = threadIdx.x;
+    const int r = t % RPB, tr = t / RPB;
+    const int64_t j = (int64_t)blockIdx.x * RPB + r;
+    C<T> *my = lds + r * CF::REG;
+    TwReg<T, L, NTR> twr;
+    twr.load(tw, 2, tr);
+
+    const int f0 = var_all(V) ? 0 : (int)blockIdx.y;
+    const int f1 = var_all(V) ? nfields : f0 + 1;
+    for (int f = f0; f < f1; ++f) {
+        const C<T> *row = reinterpret_cast<const C<T> *>(a.in[f] + j * a.in_pitch);
+        const T sc = a.scale[f];
+        C<T> reg[1][E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (PRUNED && e >= E / 2) {
+                reg[0][e] = mk<T>(0, 0);
+            } else {
+                C<T> v = row[tr + NTR * e];
+                reg[0][e] = mk<T>(v.x * sc, v.y * sc);
+            }
+        }
+        fft_multi<T, L, NTR, -1, 1>(reg, my, 0, twr, tr);
+#pragma unroll
+        for (int e = 0; e < E; ++e) my[pidx(tr + NTR * e)] = reg[0][e];
+        __syncthreads();
+        C<T> *dst = a.out + f * a.out_fstride + j;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tr + NTR * e;
+            const C<T> zk = reg[0][e];
+            const C<T> zn = my[pidx((L - k) & (L - 1))];
+            const C<T> w = tw[k];
+            const T px = zk.x + zn.x, py = zk.y - zn.y;
+            const T qx = zk.x - zn.x, qy = zk.y + zn.y;
+            dst[(int64_t)k * a.out_pitch] =
+                mk<T>((T)0.5 * (px + w.x * qy + w.y * qx), (T)0.5 * (py - w.x * qx + w.y * qy));
+        }
+        if (tr == 0) dst[(int64_t)L * a.out_pitch] = mk<T>(reg[0][0].x - reg[0][0].y, (T)0);
+        __syncthreads();  // the next field's first pass reuses this row's LDS
+    }
+}
+
+// ---------------------------------------------------------------------------
+// column: for each input field, forward transform of the (zero-padded)
+// column, product with the kernel spectra of both force components, then
+// inverse transforms of the accumulated force spectra.
+//
+// Kernel spectra are stored as one real quadrant per kind (ky in [0, M/2]):
+// kinds {x0, y0} are purely imaginary, the others real; a negative ky takes
+// the kind's parity in y.  Corner-family spectra carry the phase
+// exp(-i pi (kx + ky)/M) (targets half a cell from the source lattice),
+// applied once to the accumulated sums.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int parity_y(int kind) {
+    // x0 even, xx even, xy odd, y0 odd, yx odd, yy even (in y)
+    return (kind == 2 || kind == 3 || kind == 4) ? -1 : 1;
+}
+
+template <typename T, int M, int E, int NFAM>
+__device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, const ColArgs<T> &a,
+                                        int kx, int t) {
+    constexpr int NT = M / E, H = M / 2;
+#pragma unroll
+    for (int fam = 0; fam < NFAM; ++fam) {
+        const T *qx = a.q[fam] + f * a.q_kstride + (int64_t)kx * a.q_pitch;
+        const T *qy = a.q[fam] + (3 + f) * a.q_kstride + (int64_t)kx * a.q_pitch;
+        const T sx = (T)parity_y(f), sy = (T)parity_y(3 + f);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ky = t + NT * e;
+            const bool neg = ky > H;
+            const int kq = neg ? M - ky : ky;
+            T vx = qx[kq], vy = qy[kq];
+            if (neg) {
+                vx *= sx;
+                vy *= sy;
+            }
+            const C<T> X = x[e];
+            if (f == 0) {  // imaginary spectra: X * (i v)
+                acc[2 * fam][e].x -= X.y * vx;
+                acc[2 * fam][e].y += X.x * vx;
+                acc[2 * fam + 1][e].x -= X.y * vy;
+                acc[2 * fam + 1][e].y += X.x * vy;
+            } else {
+                acc[2 * fam][e].x += X.x * vx;
+                acc[2 * fam][e].y += X.y * vx;
+                acc[2 * fam + 1][e].x += X.x * vy;
+                acc[2 * fam + 1][e].y += X.y * vy;
+            }
+        }
+    }
+}
+
+template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
+    static constexpr int NB = var_all(V) ? cmax(NF, 2 * NFAM) : 1;
+    static constexpr int N = NB * lds_region<M>();
+};
+// a column variant exists if its transform has at least 2 threads and its
+// LDS fits the 160 KB of a gfx950 CU
+template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok() {
+    return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>) <= 163840;
+}
+
+template <typename T, int M, int V, int NF, int NFAM>
+__global__ void __launch_bounds__((M / var_e(V)))
+    k_col(ColArgs<T> a, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
+    constexpr int E = var_e(V), NT = M / E, H = M / 2;
+    constexpr int REG = lds_region<M>();
+    __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM>::N];
+    const int t = threadIdx.x;
+    const int kx = blockIdx.x;
+    TwReg<T, M, NT> twr;
+    twr.load(tw, 1, t);
+
+    C<T> acc[2 * NFAM][E];
+#pragma unroll
+    for (int g = 0; g < 2 * NFAM; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[g][e] = mk<T>(0, 0);
+
+    if constexpr (var_all(V)) {
+        C<T> x[NF][E];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const C<T> *src = a.in + f * a.in_fstride + (int64_t)kx * a.in_pitch;
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[f][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
+        }
+        fft_multi<T, M, NT, -1, NF>(x, lds, REG, twr, t);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) col_mac<T, M, E, NFAM>(acc, x[f], f, a, kx, t);
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            C<T> x[1][E];
+            const C<T> *src = a.in + f * a.in_fstride + (int64_t)kx * a.in_pitch;
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[0][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
+            fft_multi<T, M, NT, -1, 1>(x, lds, REG, twr, t);
+            col_mac<T, M, E, NFAM>(acc, x[0], f, a, kx, t);
+        }
+    }
+    if constexpr (NFAM == 2) {
+        const C<T> px = ph[kx];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ky = t + NT * e;
+            const C<T> py = ky <= H ? ph[ky] : cconj<T>(ph[M - ky]);
+            const C<T> p = cmul<T>(px, py);
+            acc[2][e] = cmul<T>(acc[2][e], p);
+            acc[3][e] = cmul<T>(acc[3][e], p);
+        }
+    }
+    if constexpr (var_all(V)) {
+        fft_multi<T, M, NT, +1, 2 * NFAM>(acc, lds, REG, twr, t);
+    } else {
+#pragma unroll
+        for (int g = 0; g < 2 * NFAM; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, REG, twr, t);
+    }
+#pragma unroll
+    for (int g = 0; g < 2 * NFAM; ++g) {
+        C<T> *dst = a.out + g * a.out_gstride + (int64_t)kx * a.out_pitch;
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) dst[t + NT * e] = acc[g][e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row inverse: Y[k], k in [0, L] (Hermitian half) -> y[n], n < M/2, scaled
+// ---------------------------------------------------------------------------
+template <typename T, int M, int V>
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
+    k_row_inv(RowInvArgs<T> a, int nout, const C<T> *__restrict__ tw) {
+    constexpr int E = var_e(V);
+    using CF = RowCfg<T, M, E>;
+    constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
+    __shared__ C<T> lds[RPB * CF::REG];
+    const int t = threadIdx.x;
+    const int r = t % RPB, tr = t / RPB;
+    const int64_t j = (int64_t)blockIdx.x * RPB + r;
+    C<T> *my = lds + r * CF::REG;
+    TwReg<T, L, NTR> twr;
+    twr.load(tw, 2, tr);
+
+    const int g0 = var_all(V) ? 0 : (int)blockIdx.y;
+    const int g1 = var_all(V) ? nout : g0 + 1;
+    for (int g = g0; g < g1; ++g) {
+        const C<T> *src = a.in + g * a.in_gstride + j;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tr + NTR * e;
+            my[pidx(k)] = src[(int64_t)k * a.in_pitch];
+        }
+        if (tr == 0) my[pidx(L)] = src[(int64_t)L * a.in_pitch];
+        __syncthreads();
+        C<T> reg[1][E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tr + NTR * e;
+            C<T> yk = my[pidx(k)];
+            C<T> yn = my[pidx(L - k)];
+            if (k == 0) {  // Y[0] and Y[L] of a real signal are real
+                yk.y = 0;
+                yn.y = 0;
+            }
+            const C<T> ze = mk<T>(yk.x + yn.x, yk.y - yn.y);
+            const C<T> zo = cmulc<T>(mk<T>(yk.x - yn.x, yk.y + yn.y), tw[k]);
+            reg[0][e] = mk<T>(ze.x - zo.y, ze.y + zo.x);
+        }
+        __syncthreads();
+        fft_multi<T, L, NTR, +1, 1>(reg, my, 0, twr, tr);
+        C<T> *dst = reinterpret_cast<C<T> *>(a.out[g] + j * a.out_pitch);
+        const T sc = a.scale;
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) dst[tr + NTR * e] = mk<T>(reg[0][e].x * sc, reg[0][e].y * sc);
+        __syncthreads();  // the next output's staging reuses this row's LDS
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+#define GRAV_SWITCH_M(M, ...)                               \
+    switch (M) {                                            \
+        case 32: { constexpr int MM = 32; __VA_ARGS__; }    \
+        case 64: { constexpr int MM = 64; __VA_ARGS__; }    \
+        case 128: { constexpr int MM = 128; __VA_ARGS__; }  \
+        case 256: { constexpr int MM = 256; __VA_ARGS__; }  \
+        case 512: { constexpr int MM = 512; __VA_ARGS__; }  \
+        case 1024: { constexpr int MM = 1024; __VA_ARGS__; } \
+        case 2048: { constexpr int MM = 2048; __VA_ARGS__; } \
+        case 4096: { constexpr int MM = 4096; __VA_ARGS__; } \
+        case 8192: { constexpr int MM = 8192; __VA_ARGS__; } \
+        default: return hipErrorInvalidValue;               \
+    }
+
+template <typename T, int M> struct Dispatch {
+    template <int V>
+    static hipError_t row_fwd_v(const RowFwdArgs<T> &a, bool pruned, int nrows, int nfields,
+                                const C<T> *tw, hipStream_t s) {
+        if constexpr (!row_var_ok<M, V>()) {
+            return hipErrorInvalidValue;
+        } else {
+            using CF = RowCfg<T, M, var_e(V)>;
+            if (nrows % CF::RPB) return hipErrorInvalidValue;
+            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields);
+            if (pruned)
+                hipLaunchKernelGGL((k_row_fwd<T, M, V, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+            else
+                hipLaunchKernelGGL((k_row_fwd<T, M, V, false>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+            return hipGetLastError();
+        }
+    }
+    static hipError_t row_fwd(const RowFwdArgs<T> &a, int var, bool pruned, int nrows, int nfields,
+                              const C<T> *tw, hipStream_t s) {
+        switch (var) {
+            case 0: return row_fwd_v<0>(a, pruned, nrows, nfields, tw, s);
+            case 1: return row_fwd_v<1>(a, pruned, nrows, nfields, tw, s);
+            case 2: return row_fwd_v<2>(a, pruned, nrows, nfields, tw, s);
+            case 3: return row_fwd_v<3>(a, pruned, nrows, nfields, tw, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    template <int V, int NF, int NFAM>
+    static hipError_t col_v(const ColArgs<T> &a, const C<T> *tw, const C<T> *ph, hipStream_t s) {
+        if constexpr (!col_var_ok<T, M, V, NF, NFAM>()) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(M / 2 + 1), dim3(M / var_e(V)), 0, s, a,
+                               tw, ph);
+            return hipGetLastError();
+        }
+    }
+    template <int V>
+    static hipError_t col_nf(const ColArgs<T> &a, int nfields, int nfam, const C<T> *tw,
+                             const C<T> *ph, hipStream_t s) {
+        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1>(a, tw, ph, s);
+        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2>(a, tw, ph, s);
+        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1>(a, tw, ph, s);
+        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2>(a, tw, ph, s);
+        return hipErrorInvalidValue;
+    }
+    static hipError_t col(const ColArgs<T> &a, int var, int nfields, int nfam, const C<T> *tw,
+                          const C<T> *ph, hipStream_t s) {
+        switch (var) {
+            case 0: return col_nf<0>(a, nfields, nfam, tw, ph, s);
+            case 1: return col_nf<1>(a, nfields, nfam, tw, ph, s);
+            case 2: return col_nf<2>(a, nfields, nfam, tw, ph, s);
+            case 3: return col_nf<3>(a, nfields, nfam, tw, ph, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    template <int V>
+    static hipError_t row_inv_v(const RowInvArgs<T> &a, int nrows, int nout, const C<T> *tw,
+                                hipStream_t s) {
+        if constexpr (!row_var_ok<M, V>()) {
+            return hipErrorInvalidValue;
+        } else {
+            using CF = RowCfg<T, M, var_e(V)>;
+            if (nrows % CF::RPB) return hipErrorInvalidValue;
+            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nout);
+            hipLaunchKernelGGL((k_row_inv<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
+            return hipGetLastError();
+        }
+    }
+    static hipError_t row_inv(const RowInvArgs<T> &a, int var, int nrows, int nout, const C<T> *tw,
+                              hipStream_t s) {
+        switch (var) {
+            case 0: return row_inv_v<0>(a, nrows, nout, tw, s);
+            case 1: return row_inv_v<1>(a, nrows, nout, tw, s);
+            case 2: return row_inv_v<2>(a, nrows, nout, tw, s);
+            case 3: return row_inv_v<3>(a, nrows, nout, tw, s);
+        }
+        return hipErrorInvalidValue;
+    }
+};
+
+template <typename T>
+hipError_t launch_row_fwd_impl(const RowFwdArgs<T> &a, int M, int var, bool pruned, int nrows,
+                               int nfields, const C<T> *tw, hipStream_t s) {
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_fwd(a, var, pruned, nrows, nfields, tw, s)))
+}
+template <typename T>
+hipError_t launch_col_impl(const ColArgs<T> &a, int M, int var, int nfields, int nfam, const C<T> *tw,
+                           const C<T> *ph, hipStream_t s) {
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, var, nfields, nfam, tw, ph, s)))
+}
+template <typename T>
+hipError_t launch_row_inv_impl(const RowInvArgs<T> &a, int M, int var, int nrows, int nout,
+                               const C<T> *tw, hipStream_t s) {
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_inv(a, var, nrows, nout, tw, s)))
+}
+
+template <typename T>
+hipError_t launch_row_fwd(const RowFwdArgs<T> &a, int M, int var, bool pruned, int nrows,
+                          int nfields, const C<T> *tw, hipStream_t s) {
+    return launch_row_fwd_impl<T>(a, M, var, pruned, nrows, nfields, tw, s);
+}
+template <typename T>
+hipError_t launch_col(const ColArgs<T> &a, int M, int var, int nfields, int nfam, const C<T> *tw,
+                      const C<T> *ph, hipStream_t s) {
+    return launch_col_impl<T>(a, M, var, nfields, nfam, tw, ph, s);
+}
+template <typename T>
+hipError_t launch_row_inv(const RowInvArgs<T> &a, int M, int var, int nrows, int nout,
+                          const C<T> *tw, hipStream_t s) {
+    return launch_row_inv_impl<T>(a, M, var, nrows, nout, tw, s);
+}
+
+}  // namespace grav
