@@ -203,14 +203,15 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
     for (int kind = 0; kind < 6; ++kind) {
         ta.kind = kind;
         hip_check(launch_ktable(ta, s), "kernel table build");
-        RowFwdArgs<double> ra{};
+        Pack<RowFwdArgs<double>> rp{};
+        RowFwdArgs<double> &ra = rp.a[0];
         ra.in[0] = (const double *)table.p;
         ra.scale[0] = 1.0;
         ra.in_pitch = M;
         ra.out = (C<double> *)rows.p;
         ra.out_pitch = M;
         ra.out_fstride = 0;
-        hip_check(launch_row_fwd<double>(ra, M, 0, false, M, 1, (const C<double> *)tw64->tw.p, s),
+        hip_check(launch_row_fwd<double>(rp, 1, M, 0, false, M, 1, (const C<double> *)tw64->tw.p, s),
                   "kernel table row transform");
         const int imag = (kind == 0 || kind == 3) ? 1 : 0;
         if (prec) {
@@ -385,101 +386,153 @@ const char *const kStagesAmr[] = {"inject", "row_fwd", "col", "row_inv", "gather
 
 int n_stages(const gravity_plan_s &p) { return p.amr ? 5 : 3; }
 
-// ev: optional array of n_stages(p) + 1 events recorded between the stages
-template <typename T>
-void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const void *dsy, void *fx,
-             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+// One solve's arguments (device pointers) and workspace.
+struct Item {
+    const gravity_plan_s *p;
+    const void *s, *dx, *dy;
+    void *fx, *fy;
+    char *ws;
+};
+
+// Solves that can share every launch: same precision, size, fields, layout
+// kind and kernel variants.
+bool same_group(const gravity_plan_s &a, const gravity_plan_s &b) {
+    return a.prec == b.prec && a.M == b.M && a.nfields == b.nfields && a.amr == b.amr &&
+           a.var_rf == b.var_rf && a.var_col == b.var_col && a.var_ri == b.var_ri &&
+           a.device == b.device;
+}
+
+// Queue n (1..kPack) solves of one group; ev: optional n_stages + 1 events
+// recorded between the stages.
+template <typename T> void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr) {
+    const gravity_plan_s &p0 = *it[0].p;
+    const int nf = p0.nf, M = p0.M, H = M / 2;
+    const int NF = p0.nfields;
+    const int nfam = p0.amr ? 2 : 1;
+    const C<T> *tw = (const C<T> *)p0.tw->tw.p;
+    const C<T> *ph = (const C<T> *)p0.tw->ph.p;
+    const int64_t colsz = (int64_t)(H + 1) * nf;
+    const int64_t n2 = (int64_t)nf * nf;
     int stage = 0;
     auto mark = [&]() {
         if (ev) hip_check(hipEventRecord(ev[stage++], s), "hipEventRecord");
     };
-    const int n = p.nf, M = p.M, H = M / 2;
-    const int NF = p.nfields;
-    const C<T> *tw = (const C<T> *)p.tw->tw.p;
-    const C<T> *ph = (const C<T> *)p.tw->ph.p;
-    C<T> *A = (C<T> *)(ws + p.off_a);
-    C<T> *B = (C<T> *)(ws + p.off_b);
-    const int64_t colsz = (int64_t)(H + 1) * n;
-    const T h = (T)(p.h0 / (double)(1 << (p.nlevels - 1)));
 
-    RowFwdArgs<T> ra{};
-    if (!p.amr) {
-        ra.in[0] = (const T *)sigma;
-        ra.in[1] = (const T *)dsx;
-        ra.in[2] = (const T *)dsy;
-    } else {
-        T *W = (T *)(ws + p.off_w);
-        const int64_t n2 = (int64_t)n * n;
-        InjectArgs<T> ia{};
-        ia.s = (const T *)sigma;
-        ia.dx = (const T *)dsx;
-        ia.dy = (const T *)dsy;
-        ia.owner = (const int32_t *)p.owner.p;
-        ia.w0 = W;
-        ia.w1 = W + n2;
-        ia.w2 = W + 2 * n2;
-        ia.nf = n;
-        ia.hf = h;
-        ia.slopes = NF == 3;
-        mark();
-        hip_check(launch_inject<T>(ia, s), "inject");
-        ra.in[0] = W;
-        ra.in[1] = W + n2;
-        ra.in[2] = W + 2 * n2;
+    Pack<RowFwdArgs<T>> rf{};
+    for (int i = 0; i < n; ++i) {
+        const gravity_plan_s &p = *it[i].p;
+        const T h = (T)(p.h0 / (double)(1 << (p.nlevels - 1)));
+        RowFwdArgs<T> &ra = rf.a[i];
+        if (!p.amr) {
+            ra.in[0] = (const T *)it[i].s;
+            ra.in[1] = (const T *)it[i].dx;
+            ra.in[2] = (const T *)it[i].dy;
+        } else {
+            T *W = (T *)(it[i].ws + p.off_w);
+            ra.in[0] = W;
+            ra.in[1] = W + n2;
+            ra.in[2] = W + 2 * n2;
+        }
+        ra.scale[0] = (T)1;
+        ra.scale[1] = h;
+        ra.scale[2] = h;
+        ra.in_pitch = nf;
+        ra.out = (C<T> *)(it[i].ws + p.off_a);
+        ra.out_pitch = nf;
+        ra.out_fstride = colsz;
     }
-    ra.scale[0] = (T)1;
-    ra.scale[1] = h;
-    ra.scale[2] = h;
-    ra.in_pitch = n;
-    ra.out = A;
-    ra.out_pitch = n;
-    ra.out_fstride = colsz;
-    mark();
-    hip_check(launch_row_fwd<T>(ra, M, p.var_rf, true, n, NF, tw, s), "row transform");
-
-    ColArgs<T> ca{};
-    ca.in = A;
-    ca.in_pitch = n;
-    ca.in_fstride = colsz;
-    ca.q[0] = (const T *)p.centre->q.p;
-    ca.q[1] = p.amr ? (const T *)p.corner->q.p : (const T *)p.centre->q.p;
-    ca.q_pitch = p.centre->q_pitch;
-    ca.q_kstride = p.centre->q_kstride;
-    ca.out = B;
-    ca.out_pitch = n;
-    ca.out_gstride = colsz;
-    const int nfam = p.amr ? 2 : 1;
-    mark();
-    hip_check(launch_col<T>(ca, M, p.var_col, NF, nfam, tw, ph, s), "column transform");
-
-    RowInvArgs<T> ia{};
-    ia.in = B;
-    ia.in_pitch = n;
-    ia.in_gstride = colsz;
-    ia.out_pitch = n;
-    ia.scale = (T)(p.G / ((double)M * (double)M));
-    if (!p.amr) {
-        ia.out[0] = (T *)fx;
-        ia.out[1] = (T *)fy;
+    if (p0.amr) {
+        Pack<InjectArgs<T>> ip{};
+        for (int i = 0; i < n; ++i) {
+            const gravity_plan_s &p = *it[i].p;
+            InjectArgs<T> &ia = ip.a[i];
+            ia.s = (const T *)it[i].s;
+            ia.dx = (const T *)it[i].dx;
+            ia.dy = (const T *)it[i].dy;
+            ia.owner = (const int32_t *)p.owner.p;
+            ia.w0 = (T *)rf.a[i].in[0];
+            ia.w1 = (T *)rf.a[i].in[1];
+            ia.w2 = (T *)rf.a[i].in[2];
+            ia.nf = nf;
+            ia.hf = rf.a[i].scale[1];
+            ia.slopes = NF == 3;
+        }
         mark();
-        hip_check(launch_row_inv<T>(ia, M, p.var_ri, n, 2, tw, s), "inverse row transform");
-        mark();
-    } else {
-        T *O = (T *)(ws + p.off_o);
-        const int64_t n2 = (int64_t)n * n;
-        for (int g = 0; g < 4; ++g) ia.out[g] = O + g * n2;
-        mark();
-        hip_check(launch_row_inv<T>(ia, M, p.var_ri, n, 4, tw, s), "inverse row transform");
-        GatherArgs<T> ga{};
-        ga.gmap = (const int32_t *)p.gmap.p;
-        for (int g = 0; g < 4; ++g) ga.o[g] = O + g * n2;
-        ga.fx = (T *)fx;
-        ga.fy = (T *)fy;
-        ga.n = p.ncells;
-        mark();
-        hip_check(launch_gather<T>(ga, s), "gather");
-        mark();
+        hip_check(launch_inject<T>(ip, n, nf, s), "inject");
     }
+    mark();
+    hip_check(launch_row_fwd<T>(rf, n, M, p0.var_rf, true, nf, NF, tw, s), "row transform");
+
+    Pack<ColArgs<T>> cp{};
+    for (int i = 0; i < n; ++i) {
+        const gravity_plan_s &p = *it[i].p;
+        ColArgs<T> &ca = cp.a[i];
+        ca.in = rf.a[i].out;
+        ca.in_pitch = nf;
+        ca.in_fstride = colsz;
+        ca.q[0] = (const T *)p.centre->q.p;
+        ca.q[1] = p.amr ? (const T *)p.corner->q.p : (const T *)p.centre->q.p;
+        ca.q_pitch = p.centre->q_pitch;
+        ca.q_kstride = p.centre->q_kstride;
+        ca.out = (C<T> *)(it[i].ws + p.off_b);
+        ca.out_pitch = nf;
+        ca.out_gstride = colsz;
+    }
+    mark();
+    hip_check(launch_col<T>(cp, n, M, p0.var_col, NF, nfam, tw, ph, s), "column transform");
+
+    Pack<RowInvArgs<T>> ip{};
+    for (int i = 0; i < n; ++i) {
+        const gravity_plan_s &p = *it[i].p;
+        RowInvArgs<T> &ia = ip.a[i];
+        ia.in = cp.a[i].out;
+        ia.in_pitch = nf;
+        ia.in_gstride = colsz;
+        ia.out_pitch = nf;
+        ia.scale = (T)(p.G / ((double)M * (double)M));
+        if (!p.amr) {
+            ia.out[0] = (T *)it[i].fx;
+            ia.out[1] = (T *)it[i].fy;
+        } else {
+            T *O = (T *)(it[i].ws + p.off_o);
+            for (int g = 0; g < 4; ++g) ia.out[g] = O + g * n2;
+        }
+    }
+    mark();
+    hip_check(launch_row_inv<T>(ip, n, M, p0.var_ri, nf, 2 * nfam, tw, s), "inverse row transform");
+
+    if (p0.amr) {
+        Pack<GatherArgs<T>> gp{};
+        int64_t maxc = 0;
+        for (int i = 0; i < n; ++i) {
+            const gravity_plan_s &p = *it[i].p;
+            GatherArgs<T> &ga = gp.a[i];
+            ga.gmap = (const int32_t *)p.gmap.p;
+            for (int g = 0; g < 4; ++g) ga.o[g] = ip.a[i].out[g];
+            ga.fx = (T *)it[i].fx;
+            ga.fy = (T *)it[i].fy;
+            ga.n = p.ncells;
+            maxc = std::max<int64_t>(maxc, p.ncells);
+        }
+        mark();
+        hip_check(launch_gather<T>(gp, n, maxc, s), "gather");
+    }
+    mark();
+}
+
+void run_items(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr) {
+    if (it[0].p->prec)
+        run_group<double>(it, n, s, ev);
+    else
+        run_group<float>(it, n, s, ev);
+}
+
+// single solve entry used by the autotuner and the profiling call
+template <typename T>
+void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const void *dsy, void *fx,
+             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+    Item it{&p, sigma, dsx, dsy, fx, fy, ws};
+    run_group<T>(&it, 1, s, ev);
 }
 
 // ---------------------------------------------------------------------------
@@ -743,11 +796,8 @@ gravity_status_t gravity_solve(gravity_plan_t p, const void *sigma, const void *
                                void *fx, void *fy, void *workspace, void *stream) {
     return guarded([&] {
         check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
-        hipStream_t s = (hipStream_t)stream;
-        if (p->prec)
-            solve_t<double>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s);
-        else
-            solve_t<float>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s);
+        Item it{p, sigma, dsx, dsy, fx, fy, (char *)workspace};
+        run_items(&it, 1, (hipStream_t)stream);
     });
 }
 
@@ -768,25 +818,32 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, con
                                      void *const *fy, void *workspace, void *stream) {
     return guarded([&] {
         if (n < 0 || (n > 0 && (!plans || !sigma || !fx || !fy))) fail(GRAVITY_EINVAL, "bad batch arguments");
+        std::vector<Item> items;
+        items.reserve(n);
         size_t off = 0;
         for (int i = 0; i < n; ++i) {
             const void *dx = dsx ? dsx[i] : nullptr;
             const void *dy = dsy ? dsy[i] : nullptr;
             char *ws = workspace ? (char *)workspace + off : nullptr;
             check_solve_args(plans[i], sigma[i], dx, dy, fx[i], fy[i], ws);
+            items.push_back(Item{plans[i], sigma[i], dx, dy, fx[i], fy[i], ws});
             off += align256(plans[i]->ws_bytes);
         }
+        // group solves that can share launches (stable order within a group)
+        std::vector<bool> done(n, false);
         hipStream_t s = (hipStream_t)stream;
-        off = 0;
+        std::vector<Item> grp;
         for (int i = 0; i < n; ++i) {
-            const void *dx = dsx ? dsx[i] : nullptr;
-            const void *dy = dsy ? dsy[i] : nullptr;
-            char *ws = (char *)workspace + off;
-            if (plans[i]->prec)
-                solve_t<double>(*plans[i], sigma[i], dx, dy, fx[i], fy[i], ws, s);
-            else
-                solve_t<float>(*plans[i], sigma[i], dx, dy, fx[i], fy[i], ws, s);
-            off += align256(plans[i]->ws_bytes);
+            if (done[i]) continue;
+            grp.clear();
+            for (int j = i; j < n; ++j) {
+                if (!done[j] && same_group(*items[i].p, *items[j].p)) {
+                    grp.push_back(items[j]);
+                    done[j] = true;
+                }
+            }
+            for (size_t k = 0; k < grp.size(); k += kPack)
+                run_items(grp.data() + k, (int)std::min<size_t>(kPack, grp.size() - k), s);
         }
     });
 }

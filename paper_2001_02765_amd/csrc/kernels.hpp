@@ -60,6 +60,13 @@ template <typename T> struct GatherArgs {
     int64_t n;
 };
 
+// Up to kPack independent solves of one size share a launch: the kernels
+// take their argument blocks by value in a Pack and pick item blockIdx.z.
+constexpr int kPack = 8;
+template <typename A> struct Pack {
+    A a[kPack];
+};
+
 struct TableArgs {
     double *out;  // M x M circulant table, row-major [my][mx]
     int M;
@@ -75,17 +82,20 @@ constexpr int kNumVariants = 4;
 bool row_variant_valid(int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam);
 
+// Launchers: n (1..kPack) items of the same size and kind in one launch.
 template <typename T>
-hipError_t launch_row_fwd(const RowFwdArgs<T> &a, int M, int var, bool pruned, int nrows,
-                          int nfields, const C<T> *tw, hipStream_t s);
+hipError_t launch_row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int M, int var, bool pruned,
+                          int nrows, int nfields, const C<T> *tw, hipStream_t s);
 template <typename T>
-hipError_t launch_col(const ColArgs<T> &a, int M, int var, int nfields, int nfam, const C<T> *tw,
-                      const C<T> *ph, hipStream_t s);
+hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfields, int nfam,
+                      const C<T> *tw, const C<T> *ph, hipStream_t s);
 template <typename T>
-hipError_t launch_row_inv(const RowInvArgs<T> &a, int M, int var, int nrows, int nout,
+hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,
                           const C<T> *tw, hipStream_t s);
-template <typename T> hipError_t launch_inject(const InjectArgs<T> &a, hipStream_t s);
-template <typename T> hipError_t launch_gather(const GatherArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_inject(const Pack<InjectArgs<T>> &a, int n, int nf, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const Pack<GatherArgs<T>> &a, int n, int64_t maxcells, hipStream_t s);
 
 hipError_t launch_ktable(const TableArgs &a, hipStream_t s);
 // forward FFT of the columns of a table's row spectra and extraction of one

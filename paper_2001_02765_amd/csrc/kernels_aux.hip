@@ -153,7 +153,8 @@ __global__ void __launch_bounds__((ExtractCfg<M>::NT))
 // ---------------------------------------------------------------------------
 // AMR injection and gather
 // ---------------------------------------------------------------------------
-template <typename T> __global__ void __launch_bounds__(256) k_inject(InjectArgs<T> a) {
+template <typename T> __global__ void __launch_bounds__(256) k_inject(Pack<InjectArgs<T>> pk) {
+    const InjectArgs<T> &a = pk.a[blockIdx.z];
     const int64_t n2 = (int64_t)a.nf * a.nf;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n2) return;
@@ -179,7 +180,8 @@ template <typename T> __global__ void __launch_bounds__(256) k_inject(InjectArgs
     }
 }
 
-template <typename T> __global__ void __launch_bounds__(256) k_gather(GatherArgs<T> a) {
+template <typename T> __global__ void __launch_bounds__(256) k_gather(Pack<GatherArgs<T>> pk) {
+    const GatherArgs<T> &a = pk.a[blockIdx.z];
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n) return;
     const int32_t m = a.gmap[c];
@@ -263,13 +265,18 @@ bool col_variant_valid(int prec, int M, int var, int nf, int nfam) {
     return false;
 }
 
-template <typename T> hipError_t launch_inject(const InjectArgs<T> &a, hipStream_t s) {
-    const int64_t n2 = (int64_t)a.nf * a.nf;
-    hipLaunchKernelGGL((k_inject<T>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, a);
+template <typename T>
+hipError_t launch_inject(const Pack<InjectArgs<T>> &a, int n, int nf, hipStream_t s) {
+    if (n < 1 || n > kPack) return hipErrorInvalidValue;
+    const int64_t n2 = (int64_t)nf * nf;
+    hipLaunchKernelGGL((k_inject<T>), dim3((unsigned)((n2 + 255) / 256), 1, n), dim3(256), 0, s, a);
     return hipGetLastError();
 }
-template <typename T> hipError_t launch_gather(const GatherArgs<T> &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+template <typename T>
+hipError_t launch_gather(const Pack<GatherArgs<T>> &a, int n, int64_t maxcells, hipStream_t s) {
+    if (n < 1 || n > kPack) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)((maxcells + 255) / 256), 1, n), dim3(256), 0, s,
+                       a);
     return hipGetLastError();
 }
 hipError_t launch_ktable(const TableArgs &a, hipStream_t s) {
@@ -286,10 +293,10 @@ hipError_t launch_col_extract(const C<double> *in, int M, TQ *q, int64_t q_pitch
     GRAV_SWITCH_M(M, return (col_extract_m<TQ, MM>(in, q, q_pitch, imag, corner, tw, ph, s)))
 }
 
-template hipError_t launch_inject<float>(const InjectArgs<float> &, hipStream_t);
-template hipError_t launch_inject<double>(const InjectArgs<double> &, hipStream_t);
-template hipError_t launch_gather<float>(const GatherArgs<float> &, hipStream_t);
-template hipError_t launch_gather<double>(const GatherArgs<double> &, hipStream_t);
+template hipError_t launch_inject<float>(const Pack<InjectArgs<float>> &, int, int, hipStream_t);
+template hipError_t launch_inject<double>(const Pack<InjectArgs<double>> &, int, int, hipStream_t);
+template hipError_t launch_gather<float>(const Pack<GatherArgs<float>> &, int, int64_t, hipStream_t);
+template hipError_t launch_gather<double>(const Pack<GatherArgs<double>> &, int, int64_t, hipStream_t);
 template hipError_t launch_col_extract<float>(const C<double> *, int, float *, int64_t, int, int,
                                               const C<double> *, const C<double> *, hipStream_t);
 template hipError_t launch_col_extract<double>(const C<double> *, int, double *, int64_t, int, int,

@@ -49,7 +49,8 @@ template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok(
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V, bool PRUNED>
 __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
-    k_row_fwd(RowFwdArgs<T> a, int nfields, const C<T> *__restrict__ tw) {
+    k_row_fwd(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
+    const RowFwdArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V);
     using CF = RowCfg<T, M, E>;
     constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
@@ -160,7 +161,8 @@ template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok(
 
 template <typename T, int M, int V, int NF, int NFAM>
 __global__ void __launch_bounds__((M / var_e(V)))
-    k_col(ColArgs<T> a, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
+    k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
+    const ColArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
     constexpr int REG = lds_region<M>();
     __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM>::N];
@@ -227,7 +229,8 @@ __global__ void __launch_bounds__((M / var_e(V)))
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V>
 __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
-    k_row_inv(RowInvArgs<T> a, int nout, const C<T> *__restrict__ tw) {
+    k_row_inv(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
+    const RowInvArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V);
     using CF = RowCfg<T, M, E>;
     constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
@@ -293,14 +296,14 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
 
 template <typename T, int M> struct Dispatch {
     template <int V>
-    static hipError_t row_fwd_v(const RowFwdArgs<T> &a, bool pruned, int nrows, int nfields,
-                                const C<T> *tw, hipStream_t s) {
+    static hipError_t row_fwd_v(const Pack<RowFwdArgs<T>> &a, int n, bool pruned, int nrows,
+                                int nfields, const C<T> *tw, hipStream_t s) {
         if constexpr (!row_var_ok<M, V>()) {
             return hipErrorInvalidValue;
         } else {
             using CF = RowCfg<T, M, var_e(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
-            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields);
+            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields, n);
             if (pruned)
                 hipLaunchKernelGGL((k_row_fwd<T, M, V, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
             else
@@ -308,100 +311,88 @@ template <typename T, int M> struct Dispatch {
             return hipGetLastError();
         }
     }
-    static hipError_t row_fwd(const RowFwdArgs<T> &a, int var, bool pruned, int nrows, int nfields,
-                              const C<T> *tw, hipStream_t s) {
+    static hipError_t row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int var, bool pruned, int nrows,
+                              int nfields, const C<T> *tw, hipStream_t s) {
         switch (var) {
-            case 0: return row_fwd_v<0>(a, pruned, nrows, nfields, tw, s);
-            case 1: return row_fwd_v<1>(a, pruned, nrows, nfields, tw, s);
-            case 2: return row_fwd_v<2>(a, pruned, nrows, nfields, tw, s);
-            case 3: return row_fwd_v<3>(a, pruned, nrows, nfields, tw, s);
+            case 0: return row_fwd_v<0>(a, n, pruned, nrows, nfields, tw, s);
+            case 1: return row_fwd_v<1>(a, n, pruned, nrows, nfields, tw, s);
+            case 2: return row_fwd_v<2>(a, n, pruned, nrows, nfields, tw, s);
+            case 3: return row_fwd_v<3>(a, n, pruned, nrows, nfields, tw, s);
         }
         return hipErrorInvalidValue;
     }
     template <int V, int NF, int NFAM>
-    static hipError_t col_v(const ColArgs<T> &a, const C<T> *tw, const C<T> *ph, hipStream_t s) {
+    static hipError_t col_v(const Pack<ColArgs<T>> &a, int n, const C<T> *tw, const C<T> *ph,
+                            hipStream_t s) {
         if constexpr (!col_var_ok<T, M, V, NF, NFAM>()) {
             return hipErrorInvalidValue;
         } else {
-            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(M / 2 + 1), dim3(M / var_e(V)), 0, s, a,
-                               tw, ph);
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(M / 2 + 1, 1, n), dim3(M / var_e(V)), 0, s,
+                               a, tw, ph);
             return hipGetLastError();
         }
     }
     template <int V>
-    static hipError_t col_nf(const ColArgs<T> &a, int nfields, int nfam, const C<T> *tw,
+    static hipError_t col_nf(const Pack<ColArgs<T>> &a, int n, int nfields, int nfam, const C<T> *tw,
                              const C<T> *ph, hipStream_t s) {
-        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1>(a, tw, ph, s);
-        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2>(a, tw, ph, s);
-        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1>(a, tw, ph, s);
-        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2>(a, tw, ph, s);
+        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1>(a, n, tw, ph, s);
+        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2>(a, n, tw, ph, s);
+        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1>(a, n, tw, ph, s);
+        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2>(a, n, tw, ph, s);
         return hipErrorInvalidValue;
     }
-    static hipError_t col(const ColArgs<T> &a, int var, int nfields, int nfam, const C<T> *tw,
-                          const C<T> *ph, hipStream_t s) {
+    static hipError_t col(const Pack<ColArgs<T>> &a, int n, int var, int nfields, int nfam,
+                          const C<T> *tw, const C<T> *ph, hipStream_t s) {
         switch (var) {
-            case 0: return col_nf<0>(a, nfields, nfam, tw, ph, s);
-            case 1: return col_nf<1>(a, nfields, nfam, tw, ph, s);
-            case 2: return col_nf<2>(a, nfields, nfam, tw, ph, s);
-            case 3: return col_nf<3>(a, nfields, nfam, tw, ph, s);
+            case 0: return col_nf<0>(a, n, nfields, nfam, tw, ph, s);
+            case 1: return col_nf<1>(a, n, nfields, nfam, tw, ph, s);
+            case 2: return col_nf<2>(a, n, nfields, nfam, tw, ph, s);
+            case 3: return col_nf<3>(a, n, nfields, nfam, tw, ph, s);
         }
         return hipErrorInvalidValue;
     }
     template <int V>
-    static hipError_t row_inv_v(const RowInvArgs<T> &a, int nrows, int nout, const C<T> *tw,
-                                hipStream_t s) {
+    static hipError_t row_inv_v(const Pack<RowInvArgs<T>> &a, int n, int nrows, int nout,
+                                const C<T> *tw, hipStream_t s) {
         if constexpr (!row_var_ok<M, V>()) {
             return hipErrorInvalidValue;
         } else {
             using CF = RowCfg<T, M, var_e(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
-            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nout);
+            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nout, n);
             hipLaunchKernelGGL((k_row_inv<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
             return hipGetLastError();
         }
     }
-    static hipError_t row_inv(const RowInvArgs<T> &a, int var, int nrows, int nout, const C<T> *tw,
-                              hipStream_t s) {
+    static hipError_t row_inv(const Pack<RowInvArgs<T>> &a, int n, int var, int nrows, int nout,
+                              const C<T> *tw, hipStream_t s) {
         switch (var) {
-            case 0: return row_inv_v<0>(a, nrows, nout, tw, s);
-            case 1: return row_inv_v<1>(a, nrows, nout, tw, s);
-            case 2: return row_inv_v<2>(a, nrows, nout, tw, s);
-            case 3: return row_inv_v<3>(a, nrows, nout, tw, s);
+            case 0: return row_inv_v<0>(a, n, nrows, nout, tw, s);
+            case 1: return row_inv_v<1>(a, n, nrows, nout, tw, s);
+            case 2: return row_inv_v<2>(a, n, nrows, nout, tw, s);
+            case 3: return row_inv_v<3>(a, n, nrows, nout, tw, s);
         }
         return hipErrorInvalidValue;
     }
 };
 
 template <typename T>
-hipError_t launch_row_fwd_impl(const RowFwdArgs<T> &a, int M, int var, bool pruned, int nrows,
-                               int nfields, const C<T> *tw, hipStream_t s) {
-    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_fwd(a, var, pruned, nrows, nfields, tw, s)))
+hipError_t launch_row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int M, int var, bool pruned,
+                          int nrows, int nfields, const C<T> *tw, hipStream_t s) {
+    if (n < 1 || n > kPack) return hipErrorInvalidValue;
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_fwd(a, n, var, pruned, nrows, nfields, tw, s)))
 }
 template <typename T>
-hipError_t launch_col_impl(const ColArgs<T> &a, int M, int var, int nfields, int nfam, const C<T> *tw,
-                           const C<T> *ph, hipStream_t s) {
-    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, var, nfields, nfam, tw, ph, s)))
+hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfields, int nfam,
+                      const C<T> *tw, const C<T> *ph, hipStream_t s) {
+    if (n < 1 || n > kPack) return hipErrorInvalidValue;
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, n, var, nfields, nfam, tw, ph, s)))
 }
 template <typename T>
-hipError_t launch_row_inv_impl(const RowInvArgs<T> &a, int M, int var, int nrows, int nout,
-                               const C<T> *tw, hipStream_t s) {
-    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_inv(a, var, nrows, nout, tw, s)))
-}
-
-template <typename T>
-hipError_t launch_row_fwd(const RowFwdArgs<T> &a, int M, int var, bool pruned, int nrows,
-                          int nfields, const C<T> *tw, hipStream_t s) {
-    return launch_row_fwd_impl<T>(a, M, var, pruned, nrows, nfields, tw, s);
-}
-template <typename T>
-hipError_t launch_col(const ColArgs<T> &a, int M, int var, int nfields, int nfam, const C<T> *tw,
-                      const C<T> *ph, hipStream_t s) {
-    return launch_col_impl<T>(a, M, var, nfields, nfam, tw, ph, s);
-}
-template <typename T>
-hipError_t launch_row_inv(const RowInvArgs<T> &a, int M, int var, int nrows, int nout,
+hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,
                           const C<T> *tw, hipStream_t s) {
-    return launch_row_inv_impl<T>(a, M, var, nrows, nout, tw, s);
+    if (n < 1 || n > kPack) return hipErrorInvalidValue;
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_inv(a, n, var, nrows, nout, tw, s)))
 }
 
 }  // namespace grav

@@ -228,10 +228,12 @@ def test_amr_config3_sampled(gl, prec):
 
 
 def test_batch_bitwise_equals_single(gl):
-    sizes = [64, 128, 64, 32]
+    """Mixed sizes, precisions and layouts; more same-size solves than one
+    launch carries (grouping splits them), results bit-identical to singles."""
+    sizes = [64, 128, 64, 32] + [64] * 10
     plans, ins, outs, singles = [], [], [], []
     for k, n in enumerate(sizes):
-        prec = "f32" if k % 2 else "f64"
+        prec = "f32" if (k % 2 or k >= 4) else "f64"
         p = gl.Plan(n, _prec(gl, prec))
         s, dx, dy = diskgen.random_fields(n, 40 + k)
         t = [_dev(a, prec) for a in (s, dx, dy)]
