@@ -166,6 +166,51 @@ gravity_status_t gravity_solve_profiled(gravity_plan_t plan, const void *sigma, 
 /* Name of stage `stage` of this plan's pipeline ("" if out of range). */
 const char *gravity_stage_name(gravity_plan_t plan, int32_t stage);
 
+/*
+ * Request server (continuous batching).  A server owns a device arena of
+ * `hbm_budget_bytes` (allocated once, at creation) from which each admitted
+ * request's workspace is taken, `nstreams` HIP streams of default priority,
+ * and a dispatcher thread.  gravity_server_submit() queues a solve and
+ * returns a ticket at once; the dispatcher admits pending requests in
+ * arrival order as arena space frees up (a request that does not fit waits,
+ * smaller later ones may pass it), groups admitted requests that can share
+ * kernel launches (same size, precision, layout kind) into batches of up to
+ * `max_batch`, and queues each batch on the least-loaded stream, so work of
+ * different requests overlaps on the device.  Completion is detected by a
+ * host callback on the stream; a request's latency runs from submit to that
+ * callback (host monotonic clock).  A request's result is bit-identical to a
+ * gravity_solve of the same plan and inputs, alone or in any mix.
+ * Plans and their resident spectra must outlive the requests that use them;
+ * inputs and outputs stay caller-owned and must stay valid until completion.
+ * Errors: EINVAL (bad arguments), ENOMEM (arena allocation; or, on submit, a
+ * request whose workspace exceeds the whole budget).
+ */
+typedef struct gravity_server_s *gravity_server_t;
+
+typedef struct {
+    int64_t submitted, completed, in_flight, pending;
+    double latency_p50_ms, latency_p99_ms, latency_max_ms; /* over completed requests */
+    size_t budget_bytes, bytes_in_use, peak_bytes_in_use;
+    int64_t batches, leaves_completed;
+} gravity_server_stats_t;
+
+gravity_status_t gravity_server_create(size_t hbm_budget_bytes, int32_t nstreams, int32_t max_batch,
+                                       gravity_server_t *out);
+gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t plan, const void *sigma,
+                                       const void *dsx, const void *dsy, void *fx, void *fy,
+                                       int64_t *ticket);
+/* *done = 1 once the ticket's solve has completed on the device. */
+gravity_status_t gravity_server_poll(gravity_server_t srv, int64_t ticket, int32_t *done);
+/* Block until the ticket completes; *latency_ms (optional) gets its latency. */
+gravity_status_t gravity_server_wait(gravity_server_t srv, int64_t ticket, double *latency_ms);
+/* Block until every submitted request has completed. */
+gravity_status_t gravity_server_drain(gravity_server_t srv);
+gravity_status_t gravity_server_get_stats(gravity_server_t srv, gravity_server_stats_t *stats);
+/* Clear the latency record and counters (arena and streams are kept). */
+gravity_status_t gravity_server_reset_stats(gravity_server_t srv);
+/* Drain, stop the dispatcher, release streams and arena (NULL ignored). */
+void gravity_server_destroy(gravity_server_t srv);
+
 /* Release a plan (NULL is ignored).  Spectra stay resident while another
  * plan uses them.  The caller must ensure no queued solve still uses it. */
 void gravity_plan_destroy(gravity_plan_t plan);

@@ -28,8 +28,11 @@ _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5
 # exported symbols of include/gravity.h
 SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
            "gravity_solve", "gravity_batch_workspace_bytes", "gravity_solve_batch",
-           "gravity_solve_profiled", "gravity_stage_name", "gravity_plan_destroy",
-           "gravity_cache_bytes", "gravity_last_error")
+           "gravity_solve_profiled", "gravity_stage_name", "gravity_server_create",
+           "gravity_server_submit", "gravity_server_poll", "gravity_server_wait",
+           "gravity_server_drain", "gravity_server_get_stats", "gravity_server_reset_stats",
+           "gravity_server_destroy", "gravity_plan_destroy", "gravity_cache_bytes",
+           "gravity_last_error")
 
 
 class PatchT(ctypes.Structure):
@@ -76,6 +79,33 @@ _lib.gravity_cache_bytes.argtypes = []
 _lib.gravity_cache_bytes.restype = ctypes.c_size_t
 _lib.gravity_last_error.argtypes = []
 _lib.gravity_last_error.restype = ctypes.c_char_p
+
+
+class ServerStatsT(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("in_flight", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("budget_bytes", ctypes.c_size_t),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t),
+                ("batches", ctypes.c_int64), ("leaves_completed", ctypes.c_int64)]
+
+
+_lib.gravity_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]
+_lib.gravity_server_create.restype = ctypes.c_int
+_lib.gravity_server_submit.argtypes = [_vp] * 7 + [ctypes.POINTER(ctypes.c_int64)]
+_lib.gravity_server_submit.restype = ctypes.c_int
+_lib.gravity_server_poll.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
+_lib.gravity_server_poll.restype = ctypes.c_int
+_lib.gravity_server_wait.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+_lib.gravity_server_wait.restype = ctypes.c_int
+_lib.gravity_server_drain.argtypes = [_vp]
+_lib.gravity_server_drain.restype = ctypes.c_int
+_lib.gravity_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStatsT)]
+_lib.gravity_server_get_stats.restype = ctypes.c_int
+_lib.gravity_server_reset_stats.argtypes = [_vp]
+_lib.gravity_server_reset_stats.restype = ctypes.c_int
+_lib.gravity_server_destroy.argtypes = [_vp]
+_lib.gravity_server_destroy.restype = None
 
 
 class GravityError(RuntimeError):
@@ -220,3 +250,64 @@ def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None):
     ph = (_vp * max(1, n))(*[p.handle for p in plans])
     _check(_lib.gravity_solve_batch(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
                                     _ptr(workspace), _stream_handle(stream)))
+
+
+class Server:
+    """Continuous-batching request server (see gravity_server_create).
+
+    budget_bytes: device arena for request workspaces (the HBM admission
+    budget); nstreams: HIP streams the dispatcher spreads batches over."""
+
+    def __init__(self, budget_bytes, nstreams=4, max_batch=8):
+        h = _vp()
+        _check(_lib.gravity_server_create(int(budget_bytes), int(nstreams), int(max_batch),
+                                          ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, plan, sigma, dsx, dsy, fx, fy):
+        """Queue a solve; tensors must stay alive until it completes (the
+        server keeps references until wait()).  Returns a ticket."""
+        tk = ctypes.c_int64()
+        _check(_lib.gravity_server_submit(self._h, plan.handle, _ptr(sigma), _ptr(dsx), _ptr(dsy),
+                                          _ptr(fx), _ptr(fy), ctypes.byref(tk)))
+        self._keep[tk.value] = (plan, sigma, dsx, dsy, fx, fy)
+        return tk.value
+
+    def poll(self, ticket):
+        d = ctypes.c_int32()
+        _check(_lib.gravity_server_poll(self._h, int(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket):
+        """Block until the ticket completes; returns its latency in ms."""
+        lat = ctypes.c_double()
+        try:
+            _check(_lib.gravity_server_wait(self._h, int(ticket), ctypes.byref(lat)))
+        finally:
+            self._keep.pop(int(ticket), None)
+        return lat.value
+
+    def drain(self):
+        _check(_lib.gravity_server_drain(self._h))
+        self._keep.clear()
+
+    def stats(self):
+        s = ServerStatsT()
+        _check(_lib.gravity_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStatsT._fields_}
+
+    def reset_stats(self):
+        _check(_lib.gravity_server_reset_stats(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gravity_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

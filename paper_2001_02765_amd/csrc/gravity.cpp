@@ -5,7 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -905,5 +910,351 @@ size_t gravity_cache_bytes(void) {
 }
 
 const char *gravity_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// request server (continuous batching)
+// ---------------------------------------------------------------------------
+namespace {
+
+// first-fit sub-allocator over one device allocation (offsets, 256 B units)
+class Arena {
+  public:
+    explicit Arena(size_t size) : size_(size) {
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = align256(bytes ? bytes : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes ? bytes : 1);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+  private:
+    size_t size_, used_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvRequest {
+    int64_t ticket;
+    Item item;  // ws filled at admission
+    size_t ws_bytes, off = 0;
+    Clock::time_point t_submit;
+};
+
+struct SrvTicket {
+    int done = 0;
+    gravity_status_t status = GRAVITY_OK;
+    double latency_ms = 0;
+};
+
+struct SrvBatch {
+    std::vector<SrvRequest> reqs;
+    int stream = 0;
+    hipEvent_t ev = nullptr;
+};
+
+}  // namespace
+
+struct gravity_server_s {
+    int device = 0;
+    int max_batch = kPack;
+    DevBuf arena_mem;
+    std::unique_ptr<Arena> arena;
+    std::vector<hipStream_t> streams;
+    std::vector<int> load;
+    std::vector<hipEvent_t> event_pool;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<SrvRequest> pending;
+    std::vector<SrvBatch> inflight;
+    std::unordered_map<int64_t, SrvTicket> tickets;
+    int64_t next_ticket = 1;
+    std::vector<double> latencies;
+    int64_t submitted = 0, completed = 0, batches = 0, leaves = 0;
+    size_t peak = 0;
+    bool stop = false;
+    std::thread th;
+
+    void loop();
+    void complete(SrvBatch &b, gravity_status_t st);
+};
+
+void gravity_server_s::complete(SrvBatch &b, gravity_status_t st) {
+    // called with mu held
+    const auto now = Clock::now();
+    for (auto &r : b.reqs) {
+        SrvTicket &tk = tickets[r.ticket];
+        tk.done = 1;
+        tk.status = st;
+        tk.latency_ms = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
+        if (st == GRAVITY_OK) {
+            latencies.push_back(tk.latency_ms);
+            leaves += r.item.p->nleaves;
+        }
+        arena->release(r.off, r.ws_bytes);
+        ++completed;
+    }
+    --load[b.stream];
+    event_pool.push_back(b.ev);
+}
+
+void gravity_server_s::loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        // admission: arrival order, first fit; later requests may pass one that waits
+        std::vector<SrvRequest> admitted;
+        for (auto it = pending.begin(); it != pending.end();) {
+            size_t off;
+            if (arena->alloc(it->ws_bytes, &off)) {
+                it->off = off;
+                it->item.ws = (char *)arena_mem.p + off;
+                admitted.push_back(*it);
+                it = pending.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        peak = std::max(peak, arena->used());
+        // continuous batching: group admitted requests that can share launches
+        std::vector<SrvBatch> ready;
+        std::vector<bool> used(admitted.size(), false);
+        for (size_t i = 0; i < admitted.size(); ++i) {
+            if (used[i]) continue;
+            SrvBatch b;
+            for (size_t j = i; j < admitted.size() && (int)b.reqs.size() < max_batch; ++j) {
+                if (!used[j] && same_group(*admitted[i].item.p, *admitted[j].item.p)) {
+                    b.reqs.push_back(admitted[j]);
+                    used[j] = true;
+                }
+            }
+            b.stream = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            ++load[b.stream];
+            if (event_pool.empty()) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+                event_pool.push_back(e);
+            }
+            b.ev = event_pool.back();
+            event_pool.pop_back();
+            ready.push_back(std::move(b));
+        }
+        // launch without holding the lock
+        lk.unlock();
+        std::vector<gravity_status_t> st(ready.size(), GRAVITY_OK);
+        for (size_t k = 0; k < ready.size(); ++k) {
+            SrvBatch &b = ready[k];
+            std::vector<Item> items;
+            for (auto &r : b.reqs) items.push_back(r.item);
+            try {
+                if (!b.ev) fail(GRAVITY_EDEVICE, "hipEventCreate failed");
+                run_items(items.data(), (int)items.size(), streams[b.stream]);
+                hip_check(hipEventRecord(b.ev, streams[b.stream]), "hipEventRecord");
+            } catch (const Failure &f) {
+                st[k] = f.st;
+            }
+        }
+        lk.lock();
+        for (size_t k = 0; k < ready.size(); ++k) {
+            ++batches;
+            if (st[k] != GRAVITY_OK) {
+                complete(ready[k], st[k]);
+            } else {
+                inflight.push_back(std::move(ready[k]));
+            }
+        }
+        if (!ready.empty()) cv_done.notify_all();
+        // completion polling
+        bool progressed = false;
+        for (size_t k = 0; k < inflight.size();) {
+            hipError_t q = hipEventQuery(inflight[k].ev);
+            if (q == hipErrorNotReady) {
+                ++k;
+                continue;
+            }
+            complete(inflight[k], q == hipSuccess ? GRAVITY_OK : GRAVITY_EDEVICE);
+            inflight.erase(inflight.begin() + k);
+            progressed = true;
+        }
+        if (progressed) cv_done.notify_all();
+        if (stop && pending.empty() && inflight.empty()) break;
+        if (progressed || !ready.empty()) continue;
+        if (!inflight.empty())
+            cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else
+            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+    }
+}
+
+extern "C" {
+
+gravity_status_t gravity_server_create(size_t budget, int32_t nstreams, int32_t max_batch,
+                                       gravity_server_t *out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out || nstreams < 1 || nstreams > 16 || max_batch < 1) fail(GRAVITY_EINVAL, "bad server arguments");
+        auto srv = std::make_unique<gravity_server_s>();
+        hip_check(hipGetDevice(&srv->device), "hipGetDevice");
+        srv->max_batch = std::min<int>(max_batch, kPack);
+        srv->arena_mem.alloc(budget, "server arena");
+        srv->arena = std::make_unique<Arena>(budget);
+        for (int i = 0; i < nstreams; ++i) {
+            hipStream_t s = nullptr;
+            hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+            srv->streams.push_back(s);
+            srv->load.push_back(0);
+        }
+        gravity_server_s *raw = srv.get();
+        srv->th = std::thread([raw] { raw->loop(); });
+        *out = srv.release();
+    });
+}
+
+gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t p, const void *sigma,
+                                       const void *dsx, const void *dsy, void *fx, void *fy,
+                                       int64_t *ticket) {
+    return guarded([&] {
+        if (!srv || !ticket) fail(GRAVITY_EINVAL, "NULL argument");
+        alignas(256) static char aligned_dummy;
+        check_solve_args(p, sigma, dsx, dsy, fx, fy, &aligned_dummy);
+        if (p->device != srv->device) fail(GRAVITY_EINVAL, "plan and server are on different devices");
+        const size_t ws = align256(p->ws_bytes);
+        if (ws > srv->arena->size()) fail(GRAVITY_ENOMEM, "request workspace exceeds the server budget");
+        SrvRequest r;
+        r.item = Item{p, sigma, dsx, dsy, fx, fy, nullptr};
+        r.ws_bytes = ws;
+        r.t_submit = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (srv->stop) fail(GRAVITY_EBUSY, "server is shutting down");
+            r.ticket = srv->next_ticket++;
+            srv->tickets[r.ticket] = SrvTicket{};
+            srv->pending.push_back(r);
+            ++srv->submitted;
+            *ticket = r.ticket;
+        }
+        srv->cv_work.notify_one();
+    });
+}
+
+gravity_status_t gravity_server_poll(gravity_server_t srv, int64_t ticket, int32_t *done) {
+    return guarded([&] {
+        if (!srv || !done) fail(GRAVITY_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->tickets.find(ticket);
+        if (it == srv->tickets.end()) fail(GRAVITY_EINVAL, "unknown ticket");
+        *done = it->second.done;
+        if (it->second.done && it->second.status != GRAVITY_OK) fail(it->second.status, "request failed");
+    });
+}
+
+gravity_status_t gravity_server_wait(gravity_server_t srv, int64_t ticket, double *latency_ms) {
+    return guarded([&] {
+        if (!srv) fail(GRAVITY_EINVAL, "NULL server");
+        std::unique_lock<std::mutex> lk(srv->mu);
+        auto it = srv->tickets.find(ticket);
+        if (it == srv->tickets.end()) fail(GRAVITY_EINVAL, "unknown ticket");
+        srv->cv_done.wait(lk, [&] { return srv->tickets[ticket].done != 0; });
+        SrvTicket tk = srv->tickets[ticket];
+        srv->tickets.erase(ticket);
+        if (latency_ms) *latency_ms = tk.latency_ms;
+        if (tk.status != GRAVITY_OK) fail(tk.status, "request failed on the device");
+    });
+}
+
+gravity_status_t gravity_server_drain(gravity_server_t srv) {
+    return guarded([&] {
+        if (!srv) fail(GRAVITY_EINVAL, "NULL server");
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->cv_done.wait(lk, [&] { return srv->completed == srv->submitted; });
+    });
+}
+
+gravity_status_t gravity_server_get_stats(gravity_server_t srv, gravity_server_stats_t *st) {
+    return guarded([&] {
+        if (!srv || !st) fail(GRAVITY_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        st->submitted = srv->submitted;
+        st->completed = srv->completed;
+        int64_t infl = 0;
+        for (auto &b : srv->inflight) infl += (int64_t)b.reqs.size();
+        st->in_flight = infl;
+        st->pending = (int64_t)srv->pending.size();
+        std::vector<double> l = srv->latencies;
+        auto pct = [&](double q) {
+            if (l.empty()) return 0.0;
+            size_t k = (size_t)std::min<double>((double)l.size() - 1, std::floor(q * (double)(l.size() - 1) + 0.5));
+            std::nth_element(l.begin(), l.begin() + k, l.end());
+            return l[k];
+        };
+        st->latency_p50_ms = pct(0.50);
+        st->latency_p99_ms = pct(0.99);
+        st->latency_max_ms = l.empty() ? 0.0 : *std::max_element(l.begin(), l.end());
+        st->budget_bytes = srv->arena->size();
+        st->bytes_in_use = srv->arena->used();
+        st->peak_bytes_in_use = srv->peak;
+        st->batches = srv->batches;
+        st->leaves_completed = srv->leaves;
+    });
+}
+
+gravity_status_t gravity_server_reset_stats(gravity_server_t srv) {
+    return guarded([&] {
+        if (!srv) fail(GRAVITY_EINVAL, "NULL server");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->latencies.clear();
+        srv->batches = 0;
+        srv->leaves = 0;
+        srv->submitted -= srv->completed;
+        srv->completed = 0;
+        srv->peak = srv->arena->used();
+    });
+}
+
+void gravity_server_destroy(gravity_server_t srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->th.joinable()) srv->th.join();
+    for (auto s : srv->streams) (void)hipStreamDestroy(s);
+    for (auto e : srv->event_pool)
+        if (e) (void)hipEventDestroy(e);
+    delete srv;
+}
 
 }  // extern "C"

@@ -283,3 +283,53 @@ def test_invalid_requests(gl):
     with pytest.raises(gl.GravityError) as e:
         p.solve(s, None, None)  # slopes missing
     assert e.value.status == gl.EINVAL
+
+
+def test_server_results_same_alone_and_in_mix(gl):
+    """Continuous batching: a mixed stream (sizes, precisions, uniform and AMR)
+    submitted to a server under a tight HBM budget gives every request the
+    bit-identical result of its solo solve, never exceeds the budget, and
+    reports latencies."""
+    rng = np.random.default_rng(17)
+    lay = diskgen.table10_layout()
+    lay2, s2, dx2, dy2 = diskgen.amr_config(5, n0=32, nlevels=3, thresh=0.15, a=0.05)
+    kinds = []
+    for n in (32, 64, 128, 256):
+        for prec in ("f32", "f64"):
+            kinds.append(("u", n, prec, gl.Plan(n, _prec(gl, prec))))
+    kinds.append(("a", lay, "f64", gl.Plan(lay.n0, gl.F64, x0=lay.x0, y0=lay.y0, h0=lay.h0,
+                                            nlevels=lay.nlevels, patches=lay.patches)))
+    kinds.append(("a", lay2, "f32", gl.Plan(lay2.n0, gl.F32, nlevels=lay2.nlevels,
+                                             patches=lay2.patches)))
+    budget = max(k[3].workspace_bytes for k in kinds) * 3
+    srv = gl.Server(budget, nstreams=3, max_batch=8)
+    reqs = []
+    for i in range(60):
+        kind = kinds[rng.integers(len(kinds))]
+        p = kind[3]
+        vals = [_dev(rng.random(p.n_cells), kind[2]) for _ in range(3)]
+        fx = torch.empty_like(vals[0])
+        fy = torch.empty_like(vals[0])
+        tk = srv.submit(p, *vals, fx, fy)
+        reqs.append((tk, p, vals, fx, fy))
+    lat = [srv.wait(r[0]) for r in reqs]
+    st = srv.stats()
+    assert st["completed"] == 60 and st["pending"] == 0
+    assert st["peak_bytes_in_use"] <= budget
+    assert min(lat) > 0 and st["latency_p99_ms"] >= st["latency_p50_ms"] > 0
+    torch.cuda.synchronize()
+    for tk, p, vals, fx, fy in reqs:
+        ax, ay = p.solve(*vals)
+        torch.cuda.synchronize()
+        assert torch.equal(ax, fx) and torch.equal(ay, fy)
+    srv.close()
+
+
+def test_server_rejects_oversized_request(gl):
+    p = gl.Plan(128, gl.F32)
+    srv = gl.Server(p.workspace_bytes // 2, nstreams=1)
+    t = torch.zeros(p.n_cells, device="cuda")
+    with pytest.raises(gl.GravityError) as e:
+        srv.submit(p, t, t, t, torch.empty_like(t), torch.empty_like(t))
+    assert e.value.status == gl.ENOMEM
+    srv.close()
