@@ -322,3 +322,61 @@ __device__ __forceinline__ void fft_multi(C<T> (*reg)[L / NT], C<T> *lds, int ld
 }
 
 }  // namespace grav
+
+namespace grav {
+
+// ---------------------------------------------------------------------------
+// Wave-local variant: when all NT threads of a transform are one wavefront
+// (NT = 64), an LDS exchange needs no block barrier: a wave's LDS operations
+// complete in order, so a wave-scope fence between the writes and the reads
+// is enough.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int L, int NT, int DIR, int P, int OFF>
+__device__ __forceinline__ void wpass(C<T> *reg, C<T> *lds, const TwReg<T, L, NT> &tr, int t) {
+    using PI = PassInfo<L, NT, P>;
+    constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
+    constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
+    constexpr int CNT = (NS > 1) ? B * (R - 1) : 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + NT * b;
+        const int k = j & (NS - 1);
+        C<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = reg[b + r * B];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = twm<DIR, T>(v[r], tr.w[OFF + b * (R - 1) + (r - 1)]);
+        }
+        dft<R, DIR, T>(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) reg[b + r * B] = v[r];
+        } else {
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[pidx(base + r * NS)] = v[r];
+        }
+    }
+    if constexpr (!LAST) {
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < E; ++e) reg[e] = lds[pidx(t + NT * e)];
+        wave_sync();
+        wpass<T, L, NT, DIR, P + 1, OFF + CNT>(reg, lds, tr, t);
+    }
+}
+
+// one length-L transform by the 64 lanes of a wavefront (t = lane)
+template <typename T, int L, int DIR>
+__device__ __forceinline__ void fft_wave(C<T> *reg, C<T> *lds, const TwReg<T, L, 64> &tr, int t) {
+    wpass<T, L, 64, DIR, 0, 0>(reg, lds, tr, t);
+}
+
+}  // namespace grav

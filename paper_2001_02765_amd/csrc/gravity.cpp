@@ -590,8 +590,8 @@ bool col_ok(const gravity_plan_s &p, int v) {
 
 Variants default_variants(const gravity_plan_s &p) {
     Variants v{1, 0, 1};
-    if (!row_variant_valid(p.M, v.rf)) v.rf = 0;
-    if (!row_variant_valid(p.M, v.ri)) v.ri = 0;
+    if (!row_variant_valid(p.prec, p.M, v.rf)) v.rf = 0;
+    if (!row_variant_valid(p.prec, p.M, v.ri)) v.ri = 0;
     if (!col_ok(p, v.col)) v.col = 0;
     return v;
 }
@@ -618,7 +618,7 @@ template <typename T> Variants autotune(gravity_plan_s &p) {
     double tb[3] = {1e300, 1e300, 1e300};
     const int reps = M >= 4096 ? 3 : 8;
     for (int v = 0; v < kNumVariants; ++v) {
-        const bool okr = row_variant_valid(M, v), okc = col_ok(p, v);
+        const bool okr = row_variant_valid(p.prec, M, v), okc = col_ok(p, v);
         if (!okr && !okc) continue;
         p.var_rf = okr ? v : best.rf;
         p.var_ri = okr ? v : best.ri;
@@ -646,8 +646,8 @@ void choose_variants(gravity_plan_s &p) {
     const char *force = std::getenv("GRAVITY_VARIANTS");
     if (force && *force) {
         int a = 0, b = 0, c = 0;
-        if (std::sscanf(force, "%d,%d,%d", &a, &b, &c) != 3 || !row_variant_valid(p.M, a) ||
-            !col_ok(p, b) || !row_variant_valid(p.M, c))
+        if (std::sscanf(force, "%d,%d,%d", &a, &b, &c) != 3 || !row_variant_valid(p.prec, p.M, a) ||
+            !col_ok(p, b) || !row_variant_valid(p.prec, p.M, c))
             fail(GRAVITY_EINVAL, "GRAVITY_VARIANTS must be three valid variant ids 'rf,col,ri'");
         p.var_rf = a;
         p.var_col = b;

@@ -75,11 +75,12 @@ struct TableArgs {
     double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]
 };
 
-// Kernel variants of the three solve kernels (see kernels_impl.hpp):
-// bit 1 selects 16 elements per thread (else 8), bit 0 selects all fields
-// per thread.  kNumVariants variants exist for each kernel and size.
-constexpr int kNumVariants = 4;
-bool row_variant_valid(int M, int var);
+// Kernel variants of the three solve kernels (see kernels_impl.hpp): for
+// ids 0..3, bit 1 selects 16 elements per thread (else 8) and bit 0 all
+// fields per thread; row ids 4, 5 are the wave-per-row kernels (one field
+// per block / all fields per block).  Validity depends on size and precision.
+constexpr int kNumVariants = 6;
+bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam);
 
 // Launchers: n (1..kPack) items of the same size and kind in one launch.

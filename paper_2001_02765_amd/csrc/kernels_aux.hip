@@ -208,14 +208,19 @@ static hipError_t col_extract_m(const C<double> *in, TQ *q, int64_t q_pitch, int
     return hipGetLastError();
 }
 
-template <int M> static bool row_ok(int var) {
+template <typename T, int M> static bool row_ok_t(int var) {
     switch (var) {
-        case 0: return row_var_ok<M, 0>();
-        case 1: return row_var_ok<M, 1>();
-        case 2: return row_var_ok<M, 2>();
-        case 3: return row_var_ok<M, 3>();
+        case 0: return row_var_ok<T, M, 0>();
+        case 1: return row_var_ok<T, M, 1>();
+        case 2: return row_var_ok<T, M, 2>();
+        case 3: return row_var_ok<T, M, 3>();
+        case 4: return row_var_ok<T, M, 4>();
+        case 5: return row_var_ok<T, M, 5>();
     }
     return false;
+}
+template <int M> static bool row_ok(int prec, int var) {
+    return prec ? row_ok_t<double, M>(var) : row_ok_t<float, M>(var);
 }
 template <typename T, int M, int NF, int NFAM> static bool col_ok(int var) {
     switch (var) {
@@ -236,17 +241,17 @@ template <typename T, int M> static bool col_ok_k(int var, int nf, int nfam) {
 template <int M> static bool col_ok_p(int prec, int var, int nf, int nfam) {
     return prec ? col_ok_k<double, M>(var, nf, nfam) : col_ok_k<float, M>(var, nf, nfam);
 }
-bool row_variant_valid(int M, int var) {
+bool row_variant_valid(int prec, int M, int var) {
     switch (M) {
-        case 32: return row_ok<32>(var);
-        case 64: return row_ok<64>(var);
-        case 128: return row_ok<128>(var);
-        case 256: return row_ok<256>(var);
-        case 512: return row_ok<512>(var);
-        case 1024: return row_ok<1024>(var);
-        case 2048: return row_ok<2048>(var);
-        case 4096: return row_ok<4096>(var);
-        case 8192: return row_ok<8192>(var);
+        case 32: return row_ok<32>(prec, var);
+        case 64: return row_ok<64>(prec, var);
+        case 128: return row_ok<128>(prec, var);
+        case 256: return row_ok<256>(prec, var);
+        case 512: return row_ok<512>(prec, var);
+        case 1024: return row_ok<1024>(prec, var);
+        case 2048: return row_ok<2048>(prec, var);
+        case 4096: return row_ok<4096>(prec, var);
+        case 8192: return row_ok<8192>(prec, var);
     }
     return false;
 }

@@ -41,7 +41,8 @@ template <typename T, int M, int E> struct RowCfg {
 // thread (rows: in sequence; columns: in lockstep) instead of one.
 constexpr int var_e(int v) { return (v & 2) ? 16 : 8; }
 constexpr bool var_all(int v) { return (v & 1) != 0; }
-template <int M, int V> constexpr bool row_var_ok() { return M / 2 >= 2 * var_e(V); }
+template <typename T, int M> struct WaveRowCfg;
+template <typename T, int M, int V> constexpr bool row_var_ok();
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok();
 
 // ---------------------------------------------------------------------------
@@ -278,6 +279,133 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
 }
 
 // ---------------------------------------------------------------------------
+// Wave-per-row variants (ids 4, 5): each wavefront transforms one row (64
+// lanes, E = L/64 elements each) with barrier-free LDS exchanges; rows are
+// read and written contiguously by their wave, and the transposed side of
+// the block (RPB rows) goes through one LDS staging step per field, giving
+// RPB-row segments per spectral column.  Variant 5 carries every field in
+// the same block (grid y = 1), variant 4 one field per block.
+// ---------------------------------------------------------------------------
+template <typename T, int M> struct WaveRowCfg {
+    static constexpr int L = M / 2;
+    static constexpr int E = L / 64;
+    static constexpr int RPB = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int REG = lds_region<L>() + 1;  // holds X[0..L]
+    static constexpr int NTH = 64 * RPB;
+    static constexpr bool OK = (E >= 4 && E <= 16) && RPB * REG * (int)sizeof(C<T>) <= 163840;
+};
+template <typename T, int M, int V> constexpr bool row_var_ok() {
+    if constexpr (V >= 4) return WaveRowCfg<T, M>::OK;
+    else return M / 2 >= 2 * var_e(V);
+}
+
+template <typename T, int M, int V, bool PRUNED>
+__global__ void __launch_bounds__((WaveRowCfg<T, M>::NTH))
+    k_row_fwd_w(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
+    const RowFwdArgs<T> &a = pk.a[blockIdx.z];
+    using CF = WaveRowCfg<T, M>;
+    constexpr int L = CF::L, E = CF::E, RPB = CF::RPB;
+    __shared__ C<T> lds[RPB * CF::REG];
+    const int t = threadIdx.x;
+    const int r = t / 64, l = t % 64;  // wave r transforms row j0 + r
+    const int64_t j0 = (int64_t)blockIdx.x * RPB;
+    C<T> *my = lds + r * CF::REG;
+    TwReg<T, L, 64> twr;
+    twr.load(tw, 2, l);
+
+    const int f0 = (V == 5) ? 0 : (int)blockIdx.y;
+    const int f1 = (V == 5) ? nfields : f0 + 1;
+    for (int f = f0; f < f1; ++f) {
+        const C<T> *row = reinterpret_cast<const C<T> *>(a.in[f] + (j0 + r) * a.in_pitch);
+        const T sc = a.scale[f];
+        C<T> reg[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (PRUNED && e >= E / 2) {
+                reg[e] = mk<T>(0, 0);
+            } else {
+                C<T> v = row[l + 64 * e];
+                reg[e] = mk<T>(v.x * sc, v.y * sc);
+            }
+        }
+        fft_wave<T, L, -1>(reg, my, twr, l);
+#pragma unroll
+        for (int e = 0; e < E; ++e) my[pidx(l + 64 * e)] = reg[e];
+        wave_sync();
+        C<T> xk[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = l + 64 * e;
+            const C<T> zk = reg[e];
+            const C<T> zn = my[pidx((L - k) & (L - 1))];
+            const C<T> w = tw[k];
+            const T px = zk.x + zn.x, py = zk.y - zn.y;
+            const T qx = zk.x - zn.x, qy = zk.y + zn.y;
+            xk[e] = mk<T>((T)0.5 * (px + w.x * qy + w.y * qx), (T)0.5 * (py - w.x * qx + w.y * qy));
+        }
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < E; ++e) my[pidx(l + 64 * e)] = xk[e];
+        if (l == 0) my[pidx(L)] = mk<T>(reg[0].x - reg[0].y, (T)0);
+        __syncthreads();
+        // transposed store: RPB consecutive rows of each spectral column
+        C<T> *dst = a.out + f * a.out_fstride + j0;
+        for (int q = t; q < (L + 1) * RPB; q += CF::NTH) {
+            const int k = q / RPB, rr = q % RPB;
+            dst[(int64_t)k * a.out_pitch + rr] = lds[rr * CF::REG + pidx(k)];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int M, int V>
+__global__ void __launch_bounds__((WaveRowCfg<T, M>::NTH))
+    k_row_inv_w(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
+    const RowInvArgs<T> &a = pk.a[blockIdx.z];
+    using CF = WaveRowCfg<T, M>;
+    constexpr int L = CF::L, E = CF::E, RPB = CF::RPB;
+    __shared__ C<T> lds[RPB * CF::REG];
+    const int t = threadIdx.x;
+    const int r = t / 64, l = t % 64;
+    const int64_t j0 = (int64_t)blockIdx.x * RPB;
+    C<T> *my = lds + r * CF::REG;
+    TwReg<T, L, 64> twr;
+    twr.load(tw, 2, l);
+
+    const int g0 = (V == 5) ? 0 : (int)blockIdx.y;
+    const int g1 = (V == 5) ? nout : g0 + 1;
+    for (int g = g0; g < g1; ++g) {
+        const C<T> *src = a.in + g * a.in_gstride + j0;
+        for (int q = t; q < (L + 1) * RPB; q += CF::NTH) {
+            const int k = q / RPB, rr = q % RPB;
+            lds[rr * CF::REG + pidx(k)] = src[(int64_t)k * a.in_pitch + rr];
+        }
+        __syncthreads();
+        C<T> reg[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = l + 64 * e;
+            C<T> yk = my[pidx(k)];
+            C<T> yn = my[pidx(L - k)];
+            if (k == 0) {  // Y[0] and Y[L] of a real signal are real
+                yk.y = 0;
+                yn.y = 0;
+            }
+            const C<T> ze = mk<T>(yk.x + yn.x, yk.y - yn.y);
+            const C<T> zo = cmulc<T>(mk<T>(yk.x - yn.x, yk.y + yn.y), tw[k]);
+            reg[e] = mk<T>(ze.x - zo.y, ze.y + zo.x);
+        }
+        wave_sync();
+        fft_wave<T, L, +1>(reg, my, twr, l);
+        C<T> *dst = reinterpret_cast<C<T> *>(a.out[g] + (j0 + r) * a.out_pitch);
+        const T sc = a.scale;
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) dst[l + 64 * e] = mk<T>(reg[e].x * sc, reg[e].y * sc);
+        __syncthreads();  // the next output's staging overwrites every row region
+    }
+}
+
+// ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
 #define GRAV_SWITCH_M(M, ...)                               \
@@ -298,8 +426,17 @@ template <typename T, int M> struct Dispatch {
     template <int V>
     static hipError_t row_fwd_v(const Pack<RowFwdArgs<T>> &a, int n, bool pruned, int nrows,
                                 int nfields, const C<T> *tw, hipStream_t s) {
-        if constexpr (!row_var_ok<M, V>()) {
+        if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
+        } else if constexpr (V >= 4) {
+            using CF = WaveRowCfg<T, M>;
+            if (nrows % CF::RPB) return hipErrorInvalidValue;
+            dim3 grid(nrows / CF::RPB, V == 5 ? 1 : nfields, n);
+            if (pruned)
+                hipLaunchKernelGGL((k_row_fwd_w<T, M, V, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+            else
+                hipLaunchKernelGGL((k_row_fwd_w<T, M, V, false>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+            return hipGetLastError();
         } else {
             using CF = RowCfg<T, M, var_e(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
@@ -318,6 +455,8 @@ template <typename T, int M> struct Dispatch {
             case 1: return row_fwd_v<1>(a, n, pruned, nrows, nfields, tw, s);
             case 2: return row_fwd_v<2>(a, n, pruned, nrows, nfields, tw, s);
             case 3: return row_fwd_v<3>(a, n, pruned, nrows, nfields, tw, s);
+            case 4: return row_fwd_v<4>(a, n, pruned, nrows, nfields, tw, s);
+            case 5: return row_fwd_v<5>(a, n, pruned, nrows, nfields, tw, s);
         }
         return hipErrorInvalidValue;
     }
@@ -354,8 +493,14 @@ template <typename T, int M> struct Dispatch {
     template <int V>
     static hipError_t row_inv_v(const Pack<RowInvArgs<T>> &a, int n, int nrows, int nout,
                                 const C<T> *tw, hipStream_t s) {
-        if constexpr (!row_var_ok<M, V>()) {
+        if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
+        } else if constexpr (V >= 4) {
+            using CF = WaveRowCfg<T, M>;
+            if (nrows % CF::RPB) return hipErrorInvalidValue;
+            dim3 grid(nrows / CF::RPB, V == 5 ? 1 : nout, n);
+            hipLaunchKernelGGL((k_row_inv_w<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
+            return hipGetLastError();
         } else {
             using CF = RowCfg<T, M, var_e(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
@@ -371,6 +516,8 @@ template <typename T, int M> struct Dispatch {
             case 1: return row_inv_v<1>(a, n, nrows, nout, tw, s);
             case 2: return row_inv_v<2>(a, n, nrows, nout, tw, s);
             case 3: return row_inv_v<3>(a, n, nrows, nout, tw, s);
+            case 4: return row_inv_v<4>(a, n, nrows, nout, tw, s);
+            case 5: return row_inv_v<5>(a, n, nrows, nout, tw, s);
         }
         return hipErrorInvalidValue;
     }
