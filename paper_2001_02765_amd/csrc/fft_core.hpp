@@ -271,9 +271,25 @@ template <typename T, int L, int NT> struct TwReg {
     }
 };
 
-template <typename T, int L, int NT, int DIR, int NB, int P, int OFF>
-__device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, int ldss, const TwReg<T, L, NT> &tr,
-                                      int t) {
+// LDS address maps for the exchanges of fft_multi: element x of transform i.
+// SoA: one contiguous region per transform (column kernels; one pad slot per
+// 32 elements keeps Stockham strides conflict-free on 32 and 64 banks).
+// AoS: the RPB rows of a block interleaved element by element, row fastest
+// (row kernels, whose lanes are interleaved the same way; one pad slot per 8).
+struct LdsSoA {
+    int reg;
+    __device__ __forceinline__ int at(int i, int x) const { return i * reg + x + (x >> 5); }
+};
+template <int L> constexpr int soa_region() { return L + (L >> 5) + 1; }
+struct LdsAoS {
+    int stride, off;
+    __device__ __forceinline__ int at(int, int x) const { return (x + (x >> 3)) * stride + off; }
+};
+template <int L> constexpr int aos_slots() { return L + 1 + ((L + 1) >> 3) + 1; }
+
+template <typename T, int L, int NT, int DIR, int NB, int P, int OFF, class MAP>
+__device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP &map,
+                                      const TwReg<T, L, NT> &tr, int t) {
     using PI = PassInfo<L, NT, P>;
     constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
     constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
@@ -298,7 +314,7 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, int ldss, 
             } else {
                 const int base = (j / NS) * NS * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[i * ldss + pidx(base + r * NS)] = v[r];
+                for (int r = 0; r < R; ++r) lds[map.at(i, base + r * NS)] = v[r];
             }
         }
     }
@@ -307,76 +323,18 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, int ldss, 
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
-            for (int e = 0; e < E; ++e) reg[i][e] = lds[i * ldss + pidx(t + NT * e)];
+            for (int e = 0; e < E; ++e) reg[i][e] = lds[map.at(i, t + NT * e)];
         __syncthreads();
-        mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT>(reg, lds, ldss, tr, t);
+        mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT, MAP>(reg, lds, map, tr, t);
     }
 }
 
 // NB length-L transforms in lockstep; reg[i][e] holds element t + NT e of
 // transform i on entry and exit.
-template <typename T, int L, int NT, int DIR, int NB>
-__device__ __forceinline__ void fft_multi(C<T> (*reg)[L / NT], C<T> *lds, int ldss,
+template <typename T, int L, int NT, int DIR, int NB, class MAP>
+__device__ __forceinline__ void fft_multi(C<T> (*reg)[L / NT], C<T> *lds, const MAP &map,
                                           const TwReg<T, L, NT> &tr, int t) {
-    mpass<T, L, NT, DIR, NB, 0, 0>(reg, lds, ldss, tr, t);
-}
-
-}  // namespace grav
-
-namespace grav {
-
-// ---------------------------------------------------------------------------
-// Wave-local variant: when all NT threads of a transform are one wavefront
-// (NT = 64), an LDS exchange needs no block barrier: a wave's LDS operations
-// complete in order, so a wave-scope fence between the writes and the reads
-// is enough.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T, int L, int NT, int DIR, int P, int OFF>
-__device__ __forceinline__ void wpass(C<T> *reg, C<T> *lds, const TwReg<T, L, NT> &tr, int t) {
-    using PI = PassInfo<L, NT, P>;
-    constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
-    constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
-    constexpr int CNT = (NS > 1) ? B * (R - 1) : 0;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const int j = t + NT * b;
-        const int k = j & (NS - 1);
-        C<T> v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = reg[b + r * B];
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = twm<DIR, T>(v[r], tr.w[OFF + b * (R - 1) + (r - 1)]);
-        }
-        dft<R, DIR, T>(v);
-        if constexpr (LAST) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) reg[b + r * B] = v[r];
-        } else {
-            const int base = (j / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds[pidx(base + r * NS)] = v[r];
-        }
-    }
-    if constexpr (!LAST) {
-        wave_sync();
-#pragma unroll
-        for (int e = 0; e < E; ++e) reg[e] = lds[pidx(t + NT * e)];
-        wave_sync();
-        wpass<T, L, NT, DIR, P + 1, OFF + CNT>(reg, lds, tr, t);
-    }
-}
-
-// one length-L transform by the 64 lanes of a wavefront (t = lane)
-template <typename T, int L, int DIR>
-__device__ __forceinline__ void fft_wave(C<T> *reg, C<T> *lds, const TwReg<T, L, 64> &tr, int t) {
-    wpass<T, L, 64, DIR, 0, 0>(reg, lds, tr, t);
+    mpass<T, L, NT, DIR, NB, 0, 0, MAP>(reg, lds, map, tr, t);
 }
 
 }  // namespace grav

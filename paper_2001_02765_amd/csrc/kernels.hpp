@@ -75,11 +75,11 @@ struct TableArgs {
     double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]
 };
 
-// Kernel variants of the three solve kernels (see kernels_impl.hpp): for
-// ids 0..3, bit 1 selects 16 elements per thread (else 8) and bit 0 all
-// fields per thread; row ids 4, 5 are the wave-per-row kernels (one field
-// per block / all fields per block).  Validity depends on size and precision.
-constexpr int kNumVariants = 6;
+// Kernel variants of the three solve kernels (see kernels_impl.hpp): bit 1
+// selects 16 elements per thread (else 8), bit 0 all fields per thread, and
+// bit 2 (row kernels only) twice the rows per block.  Validity depends on
+// size and precision.
+constexpr int kNumVariants = 8;
 bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam);
 

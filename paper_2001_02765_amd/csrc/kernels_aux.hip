@@ -216,6 +216,8 @@ template <typename T, int M> static bool row_ok_t(int var) {
         case 3: return row_var_ok<T, M, 3>();
         case 4: return row_var_ok<T, M, 4>();
         case 5: return row_var_ok<T, M, 5>();
+        case 6: return row_var_ok<T, M, 6>();
+        case 7: return row_var_ok<T, M, 7>();
     }
     return false;
 }

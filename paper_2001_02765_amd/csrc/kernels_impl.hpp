@@ -25,41 +25,50 @@ constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
 // element), E elements per thread, RPB rows per block.  Lanes are
 // interleaved with the row index fastest, so one store instruction writes
 // RPB consecutive rows of a spectral column (transposed, coalesced output).
-template <typename T, int M, int E> struct RowCfg {
+template <typename T, int M, int E, bool DBL = false> struct RowCfg {
     static constexpr int L = M / 2;
     static constexpr int NTR = L / E;
-    static constexpr int RMAX = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int REG = lds_region<L>();
-    static constexpr int BYTES = REG * (int)sizeof(C<T>);
-    // a power of two (rows per solve are powers of two), LDS kept <= 80 KB
-    static constexpr int RPB = floor_pow2(cmax(1, cmin(RMAX, cmin(1024 / NTR, 81920 / BYTES))));
+    static constexpr int RMAX = (sizeof(T) == 4 ? 8 : 4) * (DBL ? 2 : 1);
+    static constexpr int SLOTS = aos_slots<L>();  // LDS elements per row (AoS)
+    static constexpr int BYTES = SLOTS * (int)sizeof(C<T>);
+    static constexpr int LMAX = DBL ? 163840 : 81920;
+    // a power of two (rows per solve are powers of two)
+    static constexpr int RPB = floor_pow2(cmax(1, cmin(RMAX, cmin(1024 / NTR, LMAX / BYTES))));
     static constexpr int NTH = RPB * NTR;
     static_assert((RPB & (RPB - 1)) == 0, "rows per block must be a power of two");
 };
 
 // variant ids: bit 1 selects E = 16 (else 8); bit 0 selects all fields per
-// thread (rows: in sequence; columns: in lockstep) instead of one.
+// thread (rows: in sequence; columns: in lockstep) instead of one; bit 2
+// (rows only) doubles the rows per block (128-byte transposed segments).
 constexpr int var_e(int v) { return (v & 2) ? 16 : 8; }
 constexpr bool var_all(int v) { return (v & 1) != 0; }
-template <typename T, int M> struct WaveRowCfg;
-template <typename T, int M, int V> constexpr bool row_var_ok();
+constexpr bool var_dbl(int v) { return (v & 4) != 0; }
+// a row variant exists if each row has at least 2 threads; the doubled one
+// only where it really doubles the rows per block
+template <typename T, int M, int V> constexpr bool row_var_ok() {
+    if constexpr (M / 2 < 2 * var_e(V)) return false;
+    else if constexpr (var_dbl(V))
+        return RowCfg<T, M, var_e(V), true>::RPB > RowCfg<T, M, var_e(V), false>::RPB;
+    else return true;
+}
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok();
 
 // ---------------------------------------------------------------------------
 // row forward: z[m] = x[2m] + i x[2m+1] -> Z = FFT_L(z) -> X[k], k in [0, L]
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V, bool PRUNED>
-__global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
     k_row_fwd(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
     const RowFwdArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V);
-    using CF = RowCfg<T, M, E>;
+    using CF = RowCfg<T, M, E, var_dbl(V)>;
     constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
-    __shared__ C<T> lds[RPB * CF::REG];
+    __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
     const int r = t % RPB, tr = t / RPB;
     const int64_t j = (int64_t)blockIdx.x * RPB + r;
-    C<T> *my = lds + r * CF::REG;
+    const LdsAoS map{RPB, r};
     TwReg<T, L, NTR> twr;
     twr.load(tw, 2, tr);
 
@@ -78,16 +87,16 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
                 reg[0][e] = mk<T>(v.x * sc, v.y * sc);
             }
         }
-        fft_multi<T, L, NTR, -1, 1>(reg, my, 0, twr, tr);
+        fft_multi<T, L, NTR, -1, 1>(reg, lds, map, twr, tr);
 #pragma unroll
-        for (int e = 0; e < E; ++e) my[pidx(tr + NTR * e)] = reg[0][e];
+        for (int e = 0; e < E; ++e) lds[map.at(0, tr + NTR * e)] = reg[0][e];
         __syncthreads();
         C<T> *dst = a.out + f * a.out_fstride + j;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = tr + NTR * e;
             const C<T> zk = reg[0][e];
-            const C<T> zn = my[pidx((L - k) & (L - 1))];
+            const C<T> zn = lds[map.at(0, (L - k) & (L - 1))];
             const C<T> w = tw[k];
             const T px = zk.x + zn.x, py = zk.y - zn.y;
             const T qx = zk.x - zn.x, qy = zk.y + zn.y;
@@ -152,7 +161,7 @@ __device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, co
 
 template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
     static constexpr int NB = var_all(V) ? cmax(NF, 2 * NFAM) : 1;
-    static constexpr int N = NB * lds_region<M>();
+    static constexpr int N = NB * soa_region<M>();
 };
 // a column variant exists if its transform has at least 2 threads and its
 // LDS fits the 160 KB of a gfx950 CU
@@ -165,7 +174,7 @@ __global__ void __launch_bounds__((M / var_e(V)))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
     const ColArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
-    constexpr int REG = lds_region<M>();
+    const LdsSoA map{soa_region<M>()};
     __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM>::N];
     const int t = threadIdx.x;
     const int kx = blockIdx.x;
@@ -186,7 +195,7 @@ __global__ void __launch_bounds__((M / var_e(V)))
 #pragma unroll
             for (int e = 0; e < E; ++e) x[f][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
         }
-        fft_multi<T, M, NT, -1, NF>(x, lds, REG, twr, t);
+        fft_multi<T, M, NT, -1, NF>(x, lds, map, twr, t);
 #pragma unroll
         for (int f = 0; f < NF; ++f) col_mac<T, M, E, NFAM>(acc, x[f], f, a, kx, t);
     } else {
@@ -196,7 +205,7 @@ __global__ void __launch_bounds__((M / var_e(V)))
             const C<T> *src = a.in + f * a.in_fstride + (int64_t)kx * a.in_pitch;
 #pragma unroll
             for (int e = 0; e < E; ++e) x[0][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
-            fft_multi<T, M, NT, -1, 1>(x, lds, REG, twr, t);
+            fft_multi<T, M, NT, -1, 1>(x, lds, map, twr, t);
             col_mac<T, M, E, NFAM>(acc, x[0], f, a, kx, t);
         }
     }
@@ -212,10 +221,10 @@ __global__ void __launch_bounds__((M / var_e(V)))
         }
     }
     if constexpr (var_all(V)) {
-        fft_multi<T, M, NT, +1, 2 * NFAM>(acc, lds, REG, twr, t);
+        fft_multi<T, M, NT, +1, 2 * NFAM>(acc, lds, map, twr, t);
     } else {
 #pragma unroll
-        for (int g = 0; g < 2 * NFAM; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, REG, twr, t);
+        for (int g = 0; g < 2 * NFAM; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
     }
 #pragma unroll
     for (int g = 0; g < 2 * NFAM; ++g) {
@@ -229,17 +238,17 @@ __global__ void __launch_bounds__((M / var_e(V)))
 // row inverse: Y[k], k in [0, L] (Hermitian half) -> y[n], n < M/2, scaled
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V>
-__global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
     k_row_inv(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
     const RowInvArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V);
-    using CF = RowCfg<T, M, E>;
+    using CF = RowCfg<T, M, E, var_dbl(V)>;
     constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
-    __shared__ C<T> lds[RPB * CF::REG];
+    __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
     const int r = t % RPB, tr = t / RPB;
     const int64_t j = (int64_t)blockIdx.x * RPB + r;
-    C<T> *my = lds + r * CF::REG;
+    const LdsAoS map{RPB, r};
     TwReg<T, L, NTR> twr;
     twr.load(tw, 2, tr);
 
@@ -250,16 +259,16 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = tr + NTR * e;
-            my[pidx(k)] = src[(int64_t)k * a.in_pitch];
+            lds[map.at(0, k)] = src[(int64_t)k * a.in_pitch];
         }
-        if (tr == 0) my[pidx(L)] = src[(int64_t)L * a.in_pitch];
+        if (tr == 0) lds[map.at(0, L)] = src[(int64_t)L * a.in_pitch];
         __syncthreads();
         C<T> reg[1][E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = tr + NTR * e;
-            C<T> yk = my[pidx(k)];
-            C<T> yn = my[pidx(L - k)];
+            C<T> yk = lds[map.at(0, k)];
+            C<T> yn = lds[map.at(0, L - k)];
             if (k == 0) {  // Y[0] and Y[L] of a real signal are real
                 yk.y = 0;
                 yn.y = 0;
@@ -269,139 +278,12 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V)>::NTH))
             reg[0][e] = mk<T>(ze.x - zo.y, ze.y + zo.x);
         }
         __syncthreads();
-        fft_multi<T, L, NTR, +1, 1>(reg, my, 0, twr, tr);
+        fft_multi<T, L, NTR, +1, 1>(reg, lds, map, twr, tr);
         C<T> *dst = reinterpret_cast<C<T> *>(a.out[g] + j * a.out_pitch);
         const T sc = a.scale;
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) dst[tr + NTR * e] = mk<T>(reg[0][e].x * sc, reg[0][e].y * sc);
         __syncthreads();  // the next output's staging reuses this row's LDS
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Wave-per-row variants (ids 4, 5): each wavefront transforms one row (64
-// lanes, E = L/64 elements each) with barrier-free LDS exchanges; rows are
-// read and written contiguously by their wave, and the transposed side of
-// the block (RPB rows) goes through one LDS staging step per field, giving
-// RPB-row segments per spectral column.  Variant 5 carries every field in
-// the same block (grid y = 1), variant 4 one field per block.
-// ---------------------------------------------------------------------------
-template <typename T, int M> struct WaveRowCfg {
-    static constexpr int L = M / 2;
-    static constexpr int E = L / 64;
-    static constexpr int RPB = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int REG = lds_region<L>() + 1;  // holds X[0..L]
-    static constexpr int NTH = 64 * RPB;
-    static constexpr bool OK = (E >= 4 && E <= 16) && RPB * REG * (int)sizeof(C<T>) <= 163840;
-};
-template <typename T, int M, int V> constexpr bool row_var_ok() {
-    if constexpr (V >= 4) return WaveRowCfg<T, M>::OK;
-    else return M / 2 >= 2 * var_e(V);
-}
-
-template <typename T, int M, int V, bool PRUNED>
-__global__ void __launch_bounds__((WaveRowCfg<T, M>::NTH))
-    k_row_fwd_w(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
-    const RowFwdArgs<T> &a = pk.a[blockIdx.z];
-    using CF = WaveRowCfg<T, M>;
-    constexpr int L = CF::L, E = CF::E, RPB = CF::RPB;
-    __shared__ C<T> lds[RPB * CF::REG];
-    const int t = threadIdx.x;
-    const int r = t / 64, l = t % 64;  // wave r transforms row j0 + r
-    const int64_t j0 = (int64_t)blockIdx.x * RPB;
-    C<T> *my = lds + r * CF::REG;
-    TwReg<T, L, 64> twr;
-    twr.load(tw, 2, l);
-
-    const int f0 = (V == 5) ? 0 : (int)blockIdx.y;
-    const int f1 = (V == 5) ? nfields : f0 + 1;
-    for (int f = f0; f < f1; ++f) {
-        const C<T> *row = reinterpret_cast<const C<T> *>(a.in[f] + (j0 + r) * a.in_pitch);
-        const T sc = a.scale[f];
-        C<T> reg[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            if (PRUNED && e >= E / 2) {
-                reg[e] = mk<T>(0, 0);
-            } else {
-                C<T> v = row[l + 64 * e];
-                reg[e] = mk<T>(v.x * sc, v.y * sc);
-            }
-        }
-        fft_wave<T, L, -1>(reg, my, twr, l);
-#pragma unroll
-        for (int e = 0; e < E; ++e) my[pidx(l + 64 * e)] = reg[e];
-        wave_sync();
-        C<T> xk[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = l + 64 * e;
-            const C<T> zk = reg[e];
-            const C<T> zn = my[pidx((L - k) & (L - 1))];
-            const C<T> w = tw[k];
-            const T px = zk.x + zn.x, py = zk.y - zn.y;
-            const T qx = zk.x - zn.x, qy = zk.y + zn.y;
-            xk[e] = mk<T>((T)0.5 * (px + w.x * qy + w.y * qx), (T)0.5 * (py - w.x * qx + w.y * qy));
-        }
-        wave_sync();
-#pragma unroll
-        for (int e = 0; e < E; ++e) my[pidx(l + 64 * e)] = xk[e];
-        if (l == 0) my[pidx(L)] = mk<T>(reg[0].x - reg[0].y, (T)0);
-        __syncthreads();
-        // transposed store: RPB consecutive rows of each spectral column
-        C<T> *dst = a.out + f * a.out_fstride + j0;
-        for (int q = t; q < (L + 1) * RPB; q += CF::NTH) {
-            const int k = q / RPB, rr = q % RPB;
-            dst[(int64_t)k * a.out_pitch + rr] = lds[rr * CF::REG + pidx(k)];
-        }
-        __syncthreads();
-    }
-}
-
-template <typename T, int M, int V>
-__global__ void __launch_bounds__((WaveRowCfg<T, M>::NTH))
-    k_row_inv_w(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
-    const RowInvArgs<T> &a = pk.a[blockIdx.z];
-    using CF = WaveRowCfg<T, M>;
-    constexpr int L = CF::L, E = CF::E, RPB = CF::RPB;
-    __shared__ C<T> lds[RPB * CF::REG];
-    const int t = threadIdx.x;
-    const int r = t / 64, l = t % 64;
-    const int64_t j0 = (int64_t)blockIdx.x * RPB;
-    C<T> *my = lds + r * CF::REG;
-    TwReg<T, L, 64> twr;
-    twr.load(tw, 2, l);
-
-    const int g0 = (V == 5) ? 0 : (int)blockIdx.y;
-    const int g1 = (V == 5) ? nout : g0 + 1;
-    for (int g = g0; g < g1; ++g) {
-        const C<T> *src = a.in + g * a.in_gstride + j0;
-        for (int q = t; q < (L + 1) * RPB; q += CF::NTH) {
-            const int k = q / RPB, rr = q % RPB;
-            lds[rr * CF::REG + pidx(k)] = src[(int64_t)k * a.in_pitch + rr];
-        }
-        __syncthreads();
-        C<T> reg[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = l + 64 * e;
-            C<T> yk = my[pidx(k)];
-            C<T> yn = my[pidx(L - k)];
-            if (k == 0) {  // Y[0] and Y[L] of a real signal are real
-                yk.y = 0;
-                yn.y = 0;
-            }
-            const C<T> ze = mk<T>(yk.x + yn.x, yk.y - yn.y);
-            const C<T> zo = cmulc<T>(mk<T>(yk.x - yn.x, yk.y + yn.y), tw[k]);
-            reg[e] = mk<T>(ze.x - zo.y, ze.y + zo.x);
-        }
-        wave_sync();
-        fft_wave<T, L, +1>(reg, my, twr, l);
-        C<T> *dst = reinterpret_cast<C<T> *>(a.out[g] + (j0 + r) * a.out_pitch);
-        const T sc = a.scale;
-#pragma unroll
-        for (int e = 0; e < E / 2; ++e) dst[l + 64 * e] = mk<T>(reg[e].x * sc, reg[e].y * sc);
-        __syncthreads();  // the next output's staging overwrites every row region
     }
 }
 
@@ -428,17 +310,8 @@ template <typename T, int M> struct Dispatch {
                                 int nfields, const C<T> *tw, hipStream_t s) {
         if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
-        } else if constexpr (V >= 4) {
-            using CF = WaveRowCfg<T, M>;
-            if (nrows % CF::RPB) return hipErrorInvalidValue;
-            dim3 grid(nrows / CF::RPB, V == 5 ? 1 : nfields, n);
-            if (pruned)
-                hipLaunchKernelGGL((k_row_fwd_w<T, M, V, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
-            else
-                hipLaunchKernelGGL((k_row_fwd_w<T, M, V, false>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
-            return hipGetLastError();
         } else {
-            using CF = RowCfg<T, M, var_e(V)>;
+            using CF = RowCfg<T, M, var_e(V), var_dbl(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
             dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields, n);
             if (pruned)
@@ -457,6 +330,8 @@ template <typename T, int M> struct Dispatch {
             case 3: return row_fwd_v<3>(a, n, pruned, nrows, nfields, tw, s);
             case 4: return row_fwd_v<4>(a, n, pruned, nrows, nfields, tw, s);
             case 5: return row_fwd_v<5>(a, n, pruned, nrows, nfields, tw, s);
+            case 6: return row_fwd_v<6>(a, n, pruned, nrows, nfields, tw, s);
+            case 7: return row_fwd_v<7>(a, n, pruned, nrows, nfields, tw, s);
         }
         return hipErrorInvalidValue;
     }
@@ -495,14 +370,8 @@ template <typename T, int M> struct Dispatch {
                                 const C<T> *tw, hipStream_t s) {
         if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
-        } else if constexpr (V >= 4) {
-            using CF = WaveRowCfg<T, M>;
-            if (nrows % CF::RPB) return hipErrorInvalidValue;
-            dim3 grid(nrows / CF::RPB, V == 5 ? 1 : nout, n);
-            hipLaunchKernelGGL((k_row_inv_w<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
-            return hipGetLastError();
         } else {
-            using CF = RowCfg<T, M, var_e(V)>;
+            using CF = RowCfg<T, M, var_e(V), var_dbl(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
             dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nout, n);
             hipLaunchKernelGGL((k_row_inv<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
@@ -518,6 +387,8 @@ template <typename T, int M> struct Dispatch {
             case 3: return row_inv_v<3>(a, n, nrows, nout, tw, s);
             case 4: return row_inv_v<4>(a, n, nrows, nout, tw, s);
             case 5: return row_inv_v<5>(a, n, nrows, nout, tw, s);
+            case 6: return row_inv_v<6>(a, n, nrows, nout, tw, s);
+            case 7: return row_inv_v<7>(a, n, nrows, nout, tw, s);
         }
         return hipErrorInvalidValue;
     }
