@@ -1,12 +1,10 @@
-// Solve-path kernels instantiated for float plans.
+// Row kernels instantiated for float plans.
 #include "kernels_impl.hpp"
 
 namespace grav {
 
 template hipError_t launch_row_fwd<float>(const Pack<RowFwdArgs<float>> &, int, int, int, bool, int, int,
                                         const C<float> *, hipStream_t);
-template hipError_t launch_col<float>(const Pack<ColArgs<float>> &, int, int, int, int, int,
-                                    const C<float> *, const C<float> *, hipStream_t);
 template hipError_t launch_row_inv<float>(const Pack<RowInvArgs<float>> &, int, int, int, int, int,
                                         const C<float> *, hipStream_t);
 

@@ -1,12 +1,10 @@
-// Solve-path kernels instantiated for double plans.
+// Row kernels instantiated for double plans.
 #include "kernels_impl.hpp"
 
 namespace grav {
 
 template hipError_t launch_row_fwd<double>(const Pack<RowFwdArgs<double>> &, int, int, int, bool, int, int,
                                         const C<double> *, hipStream_t);
-template hipError_t launch_col<double>(const Pack<ColArgs<double>> &, int, int, int, int, int,
-                                    const C<double> *, const C<double> *, hipStream_t);
 template hipError_t launch_row_inv<double>(const Pack<RowInvArgs<double>> &, int, int, int, int, int,
                                         const C<double> *, hipStream_t);
 
