@@ -75,6 +75,115 @@ def run_precision(gl, torch, prec, n, steps, warmup, fields):
     }
 
 
+def _timeit(torch, fn, reps):
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def amr_leg(gl, torch, reps):
+    """3-level AMR workload (base 256^2, finest 1024^2): leaf forces/s."""
+    import diskgen
+    lay, s, dx, dy = diskgen.amr_config(0)
+    out = {"workload": "AMR 3 levels, base 256^2, %d patches of 32^2, finest lattice 1024^2 "
+                       "(2048^2 FFT), Kuzmin a=0.02 + clumps" % len(lay.patches),
+           "leaves": lay.nleaves()}
+    for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
+        p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches)
+        t = [torch.from_numpy(a).to("cuda", dt) for a in (s, dx, dy)]
+        fx = torch.empty(p.n_cells, dtype=dt, device="cuda")
+        fy = torch.empty_like(fx)
+        ws = p.workspace()
+        ms = _timeit(torch, lambda: p.solve(*t, fx=fx, fy=fy, workspace=ws), reps)
+        out[name] = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3),
+                     "stages_ms": p.profile(*t, fx, fy, ws, reps=max(5, reps // 4))}
+    return out
+
+
+def batch_leg(gl, torch, reps):
+    """64 independent disks of mixed sizes in one gravity_solve_batch (FP32)
+    against the same 64 solves issued one by one."""
+    import diskgen
+    disks = diskgen.batch_disks(0)
+    plans = [gl.Plan(n, gl.F32) for (n, _, _, _) in disks]
+    ins = [[torch.from_numpy(a.ravel()).to("cuda", torch.float32) for a in d[1:]] for d in disks]
+    outs = [(torch.empty_like(i[0]), torch.empty_like(i[0])) for i in ins]
+    ws = torch.empty(gl.batch_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    args = ([i[0] for i in ins], [i[1] for i in ins], [i[2] for i in ins],
+            [o[0] for o in outs], [o[1] for o in outs])
+    ms_b = _timeit(torch, lambda: gl.solve_batch(plans, *args, ws), reps)
+    ws1 = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device="cuda")
+
+    def seq():
+        for p, i, o in zip(plans, ins, outs):
+            p.solve(*i, fx=o[0], fy=o[1], workspace=ws1)
+    ms_s = _timeit(torch, seq, reps)
+    cells = int(sum(d[0] ** 2 for d in disks))
+    return {"workload": "64 disks, n in {64..1024}, exponential/Kuzmin spirals, FP32",
+            "cells": cells, "ms_batch": ms_b, "ms_sequential": ms_s,
+            "forces_per_s_batch": cells / (ms_b * 1e-3), "forces_per_s_sequential": cells / (ms_s * 1e-3)}
+
+
+def serve_leg(gl, torch, nreq, rho=0.8, budget=8 << 30):
+    """Poisson stream of AMR solves of mixed sizes through the continuous-
+    batching server: closed-loop capacity first, then arrivals at rho times it."""
+    import diskgen
+    pool = diskgen.request_pool(0, count=8)
+    entries = []
+    for lay, prof in pool:
+        p = gl.Plan(lay.n0, gl.F32, nlevels=lay.nlevels, patches=lay.patches)
+        s, dx, dy = lay.sample(prof)
+        t = [torch.from_numpy(a).to("cuda", torch.float32) for a in (s, dx, dy)]
+        outs = [(torch.empty_like(t[0]), torch.empty_like(t[0])) for _ in range(4)]
+        entries.append((p, t, outs))
+    srv = gl.Server(budget, nstreams=4, max_batch=8)
+    rng = np.random.default_rng(1)
+    picks = rng.integers(len(entries), size=nreq)
+
+    def submit(k):
+        p, t, outs = entries[picks[k]]
+        o = outs[k % len(outs)]
+        return srv.submit(p, *t, o[0], o[1])
+
+    for k in range(min(16, nreq)):  # warm-up
+        submit(k)
+    srv.drain()
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    for k in range(nreq):
+        submit(k)
+    srv.drain()
+    cap = nreq / (time.perf_counter() - t0)
+    closed = srv.stats()
+    srv.reset_stats()
+    lam = rho * cap
+    gaps = rng.exponential(1.0 / lam, size=nreq)
+    t_arr = time.perf_counter() + np.cumsum(gaps)
+    t0 = time.perf_counter()
+    for k in range(nreq):
+        while time.perf_counter() < t_arr[k]:
+            pass
+        submit(k)
+    srv.drain()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    leaves = st["leaves_completed"]
+    srv.close()
+    return {"workload": "Poisson arrivals of AMR solves (base 128^2-2048^2, 1-3 levels, "
+                        "4-256 patches, finest lattice <= 4096^2), FP32, 8 distinct layouts",
+            "requests": nreq, "capacity_req_per_s": cap, "rate_req_per_s": lam,
+            "p50_ms": st["latency_p50_ms"], "p99_ms": st["latency_p99_ms"],
+            "max_ms": st["latency_max_ms"], "leaf_forces_per_s": leaves / wall,
+            "closed_loop_p50_ms": closed["latency_p50_ms"], "closed_loop_p99_ms": closed["latency_p99_ms"],
+            "budget_bytes": st["budget_bytes"], "peak_bytes_in_use": st["peak_bytes_in_use"],
+            "batches": st["batches"]}
+
+
 def cpu_baseline(n, fields, budget_s=15.0):
     """The oracle's direct leaf sum (exact kernels per source cell, FP64,
     compensated) on a seeded sample of target cells of the same workload,
@@ -116,6 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the AMR, batch and serving legs")
     ap.add_argument("--only", choices=["f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -178,6 +289,10 @@ def main():
         "fp64": r64,
         "roofline": roof,
     }
+    if not args.no_extra:
+        out["amr"] = amr_leg(gl, torch, max(10, args.steps // 4))
+        out["batch"] = batch_leg(gl, torch, max(5, args.steps // 20))
+        out["serve"] = serve_leg(gl, torch, nreq=max(100, 2 * args.steps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, fields)
     print(json.dumps(out), flush=True)

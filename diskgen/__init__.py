@@ -259,7 +259,8 @@ class Layout:
 def flag_layout(profile, n0, nlevels, tile=16, thresh=0.1, x0=-1.0, y0=-1.0, h0=None):
     """Refine tiles of tile x tile parent cells into (2 tile)^2 child patches
     wherever max over the tile of h_parent |grad s| / s exceeds ``thresh``;
-    level l+1 tiles are only taken inside level-l patches (proper nesting)."""
+    level l+1 tiles are only taken inside level-l patches (proper nesting).
+    Tiles are visited parent by parent, row-major within each parent."""
     if h0 is None:
         h0 = 2.0 / n0
     patches = []
@@ -268,15 +269,16 @@ def flag_layout(profile, n0, nlevels, tile=16, thresh=0.1, x0=-1.0, y0=-1.0, h0=
         hp = h0 / 2 ** (lvl - 1)
         new = []
         for par in parents:
-            for tj in range(par.j0, par.j0 + par.ny, tile):
-                for ti in range(par.i0, par.i0 + par.nx, tile):
-                    c = (np.arange(tile) + 0.5) * hp
-                    X, Y = np.meshgrid(x0 + ti * hp + c, y0 + tj * hp + c)
-                    s, dx, dy = profile(X, Y)
-                    with np.errstate(divide="ignore", invalid="ignore"):
-                        score = np.where(s > 0, hp * np.hypot(dx, dy) / s, 0.0)
-                    if np.max(score) > thresh:
-                        new.append(Patch(lvl, 2 * ti, 2 * tj, 2 * tile, 2 * tile))
+            xs = x0 + (par.i0 + np.arange(par.nx) + 0.5) * hp
+            ys = y0 + (par.j0 + np.arange(par.ny) + 0.5) * hp
+            X, Y = np.meshgrid(xs, ys)
+            s, dx, dy = profile(X, Y)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                score = np.where(s > 0, hp * np.hypot(dx, dy) / s, 0.0)
+            sc = score.reshape(par.ny // tile, tile, par.nx // tile, tile).max(axis=(1, 3))
+            for tj, ti in np.argwhere(sc > thresh):
+                new.append(Patch(lvl, 2 * (par.i0 + ti * tile), 2 * (par.j0 + tj * tile),
+                                 2 * tile, 2 * tile))
         patches.extend(new)
         parents = new
         if not new:
@@ -350,4 +352,53 @@ def batch_disks(seed, count=64, sizes=(64, 128, 256, 512, 1024)):
         X, Y = grid_centres(n)
         s, dx, dy = spiral(X, Y, base, scale, amp, 20.0, ph)
         out.append((n, s, dx, dy))
+    return out
+
+
+def limit_layout(lay, max_patches, rng):
+    """Keep at most max_patches patches, preserving nesting: patches are kept
+    level by level, each only if its parent region survived."""
+    kept = []
+    for lvl in range(1, lay.nlevels):
+        cand = [p for p in lay.patches if p.level == lvl]
+        if lvl > 1:
+            par = [p for p in kept if p.level == lvl - 1]
+
+            def inside(c):
+                return any(q.i0 <= c.i0 // 2 and c.i0 // 2 + c.nx // 2 <= q.i0 + q.nx and
+                           q.j0 <= c.j0 // 2 and c.j0 // 2 + c.ny // 2 <= q.j0 + q.ny for q in par)
+            cand = [c for c in cand if inside(c)]
+        room = max_patches - len(kept)
+        if room <= 0:
+            break
+        if len(cand) > room:
+            idx = sorted(rng.choice(len(cand), room, replace=False))
+            cand = [cand[i] for i in idx]
+        kept.extend(cand)
+    used = max([p.level for p in kept], default=0) + 1
+    return Layout(lay.n0, max(used, 1) if kept else 1, kept, lay.x0, lay.y0, lay.h0)
+
+
+def request_pool(seed, count=12, bases=(128, 256, 512, 1024, 2048), max_finest=4096):
+    """Distinct AMR request layouts for a served stream: base n0 from `bases`,
+    1-4 levels with n0 * 2^(levels-1) <= max_finest, 32x32 child patches
+    flagged on a Kuzmin (scale a ~ U[0.02, 0.2]) plus clumps profile and
+    capped at 4..256 patches.  Returns a list of (layout, profile)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n0 = int(rng.choice(bases))
+        lv_max = 1
+        while lv_max < 4 and n0 * 2 ** lv_max <= max_finest:
+            lv_max += 1
+        levels = int(rng.integers(1, lv_max + 1))
+        a = float(rng.uniform(0.02, 0.2))
+        prof = kuzmin_clumps_profile(int(rng.integers(1 << 30)), a)
+        if levels == 1:
+            lay = Layout(n0, 1, [])
+        else:
+            full = flag_layout(prof, n0, levels, 16, 0.05)
+            cap = int(np.exp(rng.uniform(np.log(4), np.log(256))))
+            lay = limit_layout(full, cap, rng)
+        out.append((lay, prof))
     return out
