@@ -76,9 +76,9 @@ struct TableArgs {
 };
 
 // Kernel variants of the three solve kernels (see kernels_impl.hpp): bit 1
-// selects 16 elements per thread (else 8), bit 0 all fields per thread, and
-// bit 2 (row kernels only) twice the rows per block.  Validity depends on
-// size and precision.
+// selects 16 elements per thread (else 8), bit 0 all fields per thread; bit
+// 2 doubles the rows per block (row kernels) or targets 4 waves per SIMD
+// (column kernel).  Validity depends on size, precision and fields.
 constexpr int kNumVariants = 8;
 bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam);

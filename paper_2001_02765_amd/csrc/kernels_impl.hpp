@@ -167,112 +167,15 @@ template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok() {
-    if constexpr (NF == 1 && V != 0) return false;
+    if constexpr (V >= 4) return false;
+    else if constexpr (NF == 1 && V != 0) return false;
     else if constexpr (M <= 256 && V > 1) return false;
     else return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>) <= 163840;
 }
 
-// Block 0 carries the two real-valued columns k_x = 0 and k_x = M/2 (the row
-// spectra of real rows are real there) as one complex column
-// z = X[., 0] + i X[., M/2]: one forward transform gives both spectra
-// (S0 = (Z + conj Z(-k))/2, SL = (Z - conj Z(-k))/2i), each is multiplied by
-// its own kernel column, and the force spectra are packed back as
-// G = F(0) + i F(M/2) (corner family: the phases exp(-i pi kx/M) of the two
-// columns are 1 and -i, so G_corner = phase_y (sum S0 K0 + sum SL KL)) for one
-// inverse transform whose real and imaginary parts are the two columns.
-template <typename T, int M, int E, int NF, int NFAM>
-__device__ __forceinline__ void col_packed(const ColArgs<T> &a, C<T> *lds, const LdsSoA &map,
-                                           const TwReg<T, M, M / E> &twr, const C<T> *ph, int t) {
-    constexpr int NT = M / E, H = M / 2;
-    C<T> acc[2 * NFAM][E];
-#pragma unroll
-    for (int g = 0; g < 2 * NFAM; ++g)
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[g][e] = mk<T>(0, 0);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        C<T> x[1][E];
-        const C<T> *s0 = a.in + f * a.in_fstride;
-        const C<T> *sL = s0 + (int64_t)H * a.in_pitch;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            x[0][e] = (e < E / 2) ? mk<T>(s0[t + NT * e].x, sL[t + NT * e].x) : mk<T>(0, 0);
-        fft_multi<T, M, NT, -1, 1>(x, lds, map, twr, t);
-#pragma unroll
-        for (int e = 0; e < E; ++e) lds[map.at(0, t + NT * e)] = x[0][e];
-        __syncthreads();
-        C<T> zm[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) zm[e] = lds[map.at(0, (M - (t + NT * e)) & (M - 1))];
-        __syncthreads();
-#pragma unroll
-        for (int fam = 0; fam < NFAM; ++fam) {
-            const T *q0x = a.q[fam] + f * a.q_kstride;
-            const T *q0y = a.q[fam] + (3 + f) * a.q_kstride;
-            const T *qLx = q0x + (int64_t)H * a.q_pitch;
-            const T *qLy = q0y + (int64_t)H * a.q_pitch;
-            const T sx = (T)parity_y(f), sy = (T)parity_y(3 + f);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int ky = t + NT * e;
-                const bool neg = ky > H;
-                const int kq = neg ? M - ky : ky;
-                T v0x = q0x[kq], v0y = q0y[kq], vLx = qLx[kq], vLy = qLy[kq];
-                if (neg) {
-                    v0x *= sx; v0y *= sy; vLx *= sx; vLy *= sy;
-                }
-                const C<T> z = x[0][e], m = zm[e];
-                const C<T> S0 = mk<T>((T)0.5 * (z.x + m.x), (T)0.5 * (z.y - m.y));
-                const C<T> SL = mk<T>((T)0.5 * (z.y + m.y), (T)-0.5 * (z.x - m.x));
-#pragma unroll
-                for (int comp = 0; comp < 2; ++comp) {
-                    const T v0 = comp ? v0y : v0x, vL = comp ? vLy : vLx;
-                    C<T> p0, pL;  // S0 * K(0), SL * K(M/2)
-                    if (f == 0) {
-                        p0 = mk<T>(-S0.y * v0, S0.x * v0);
-                        pL = mk<T>(-SL.y * vL, SL.x * vL);
-                    } else {
-                        p0 = mk<T>(S0.x * v0, S0.y * v0);
-                        pL = mk<T>(SL.x * vL, SL.y * vL);
-                    }
-                    C<T> &A = acc[2 * fam + comp][e];
-                    if (fam == 0) {  // G = F(0) + i F(M/2)
-                        A.x += p0.x - pL.y;
-                        A.y += p0.y + pL.x;
-                    } else {
-                        A.x += p0.x + pL.x;
-                        A.y += p0.y + pL.y;
-                    }
-                }
-            }
-        }
-    }
-    if constexpr (NFAM == 2) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int ky = t + NT * e;
-            const C<T> py = ky <= H ? ph[ky] : cconj<T>(ph[M - ky]);
-            acc[2][e] = cmul<T>(acc[2][e], py);
-            acc[3][e] = cmul<T>(acc[3][e], py);
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < 2 * NFAM; ++g) {
-        fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
-        C<T> *d0 = a.out + g * a.out_gstride;
-        C<T> *dL = d0 + (int64_t)H * a.out_pitch;
-#pragma unroll
-        for (int e = 0; e < E / 2; ++e) {
-            d0[t + NT * e] = mk<T>(acc[g][e].x, (T)0);
-            dL[t + NT * e] = mk<T>(acc[g][e].y, (T)0);
-        }
-    }
-}
-
 template <typename T, int M, int V, int NF, int NFAM>
-__global__ void __launch_bounds__((M / var_e(V)))
-    k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
-    const ColArgs<T> &a = pk.a[blockIdx.z];
+__device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
+                                         const C<T> *__restrict__ ph) {
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
     const LdsSoA map{soa_region<M>()};
     __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM>::N];
@@ -280,10 +183,6 @@ __global__ void __launch_bounds__((M / var_e(V)))
     const int kx = blockIdx.x;
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
-    if (kx == 0) {
-        col_packed<T, M, E, NF, NFAM>(a, lds, map, twr, ph, t);
-        return;
-    }
 
     C<T> acc[2 * NFAM][E];
 #pragma unroll
@@ -336,6 +235,12 @@ __global__ void __launch_bounds__((M / var_e(V)))
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) dst[t + NT * e] = acc[g][e];
     }
+}
+
+template <typename T, int M, int V, int NF, int NFAM>
+__global__ void __launch_bounds__((M / var_e(V)))
+    k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
+    col_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,7 +350,7 @@ template <typename T, int M> struct Dispatch {
         if constexpr (!col_var_ok<T, M, V, NF, NFAM>()) {
             return hipErrorInvalidValue;
         } else {
-            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(M / 2, 1, n), dim3(M / var_e(V)), 0, s,
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(M / 2 + 1, 1, n), dim3(M / var_e(V)), 0, s,
                                a, tw, ph);
             return hipGetLastError();
         }
