@@ -20,6 +20,18 @@
 
 namespace grav {
 
+// Block barrier for the LDS exchanges.  The compiler does not treat the
+// barrier instruction as a memory write, so it may sink LDS loads that precede
+// it into a later, conditionally executed block, where they would read LDS that
+// other waves have already overwritten.  The empty asm statements with a
+// memory clobber on both sides keep every LDS access on its own side.
+__device__ __forceinline__ void block_sync() {
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    asm volatile("" ::: "memory");
+}
+
+
 template <typename T> struct vec2;
 template <> struct vec2<float> { typedef float2 type; };
 template <> struct vec2<double> { typedef double2 type; };
@@ -180,10 +192,10 @@ __device__ __forceinline__ void st_pass(C<T> *reg, C<T> *lds, const C<T> *__rest
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        block_sync();
 #pragma unroll
         for (int e = 0; e < E; ++e) reg[e] = lds[pidx(t + NT * e)];
-        __syncthreads();
+        block_sync();
     }
 }
 
@@ -319,12 +331,12 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP 
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        block_sync();
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int e = 0; e < E; ++e) reg[i][e] = lds[map.at(i, t + NT * e)];
-        __syncthreads();
+        block_sync();
         mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT, MAP>(reg, lds, map, tr, t);
     }
 }

@@ -230,6 +230,8 @@ template <typename T, int M, int NF, int NFAM> static bool col_ok(int var) {
         case 1: return col_var_ok<T, M, 1, NF, NFAM>();
         case 2: return col_var_ok<T, M, 2, NF, NFAM>();
         case 3: return col_var_ok<T, M, 3, NF, NFAM>();
+        case 4: return col_var_ok<T, M, 4, NF, NFAM>();
+        case 6: return col_var_ok<T, M, 6, NF, NFAM>();
     }
     return false;
 }

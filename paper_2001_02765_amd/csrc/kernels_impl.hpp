@@ -90,7 +90,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
         fft_multi<T, L, NTR, -1, 1>(reg, lds, map, twr, tr);
 #pragma unroll
         for (int e = 0; e < E; ++e) lds[map.at(0, tr + NTR * e)] = reg[0][e];
-        __syncthreads();
+        block_sync();
         C<T> *dst = a.out + f * a.out_fstride + j;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
                 mk<T>((T)0.5 * (px + w.x * qy + w.y * qx), (T)0.5 * (py - w.x * qx + w.y * qy));
         }
         if (tr == 0) dst[(int64_t)L * a.out_pitch] = mk<T>(reg[0][0].x - reg[0][0].y, (T)0);
-        __syncthreads();  // the next field's first pass reuses this row's LDS
+        block_sync();  // the next field's first pass reuses this row's LDS
     }
 }
 
@@ -167,7 +167,8 @@ template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok() {
-    if constexpr (V >= 4) return false;
+    if constexpr (V >= 4 && (V == 5 || V == 7 || M < 512)) return false;
+    else if constexpr (V >= 4) return M >= 2 * var_e(V) && 2 * soa_region<M>() * (int)sizeof(C<T>) <= 163840;
     else if constexpr (NF == 1 && V != 0) return false;
     else if constexpr (M <= 256 && V > 1) return false;
     else return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>) <= 163840;
@@ -237,10 +238,85 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
     }
 }
 
+// Two adjacent columns per block (variants 4, 6): the fields are taken one
+// after the other, but each transform runs for both columns in lockstep, so
+// the twiddle registers serve two columns and (M/2+1)/2 blocks of 34 KB LDS
+// (FP32, M = 2048) run in a single dispatch round.  The last block of an odd
+// column count carries a zero dummy column (uniform control flow for the
+// block barriers, nothing loaded or stored for it).
+template <typename T, int M, int V, int NF, int NFAM>
+__device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
+                                          const C<T> *__restrict__ ph) {
+    constexpr int E = var_e(V), NT = M / E, H = M / 2;
+    const LdsSoA map{soa_region<M>()};
+    __shared__ C<T> lds[2 * soa_region<M>()];
+    const int t = threadIdx.x;
+    const int kx0 = 2 * blockIdx.x;
+    const bool has1 = kx0 + 1 <= H;
+    TwReg<T, M, NT> twr;
+    twr.load(tw, 1, t);
+
+    C<T> acc[2][2 * NFAM][E];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int g = 0; g < 2 * NFAM; ++g)
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[c][g][e] = mk<T>(0, 0);
+
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        C<T> x[2][E];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const bool ok = c == 0 || has1;
+            const C<T> *src = a.in + f * a.in_fstride + (int64_t)(kx0 + c) * a.in_pitch;
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[c][e] = (ok && e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
+        }
+        fft_multi<T, M, NT, -1, 2>(x, lds, map, twr, t);
+        col_mac<T, M, E, NFAM>(acc[0], x[0], f, a, kx0, t);
+        if (has1) col_mac<T, M, E, NFAM>(acc[1], x[1], f, a, kx0 + 1, t);
+    }
+    if constexpr (NFAM == 2) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const C<T> px = ph[(kx0 + c) <= H ? kx0 + c : H];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int ky = t + NT * e;
+                const C<T> py = ky <= H ? ph[ky] : cconj<T>(ph[M - ky]);
+                const C<T> p = cmul<T>(px, py);
+                acc[c][2][e] = cmul<T>(acc[c][2][e], p);
+                acc[c][3][e] = cmul<T>(acc[c][3][e], p);
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 2 * NFAM; ++g) {
+        C<T> y[2][E];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[c][e] = acc[c][g][e];
+        fft_multi<T, M, NT, +1, 2>(y, lds, map, twr, t);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c == 1 && !has1) break;
+            C<T> *dst = a.out + g * a.out_gstride + (int64_t)(kx0 + c) * a.out_pitch;
+#pragma unroll
+            for (int e = 0; e < E / 2; ++e) dst[t + NT * e] = y[c][e];
+        }
+    }
+}
+
 template <typename T, int M, int V, int NF, int NFAM>
 __global__ void __launch_bounds__((M / var_e(V)))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
-    col_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
+    if constexpr (var_dbl(V))
+        col2_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
+    else
+        col_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +347,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
             lds[map.at(0, k)] = src[(int64_t)k * a.in_pitch];
         }
         if (tr == 0) lds[map.at(0, L)] = src[(int64_t)L * a.in_pitch];
-        __syncthreads();
+        block_sync();
         C<T> reg[1][E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -286,13 +362,13 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
             const C<T> zo = cmulc<T>(mk<T>(yk.x - yn.x, yk.y + yn.y), tw[k]);
             reg[0][e] = mk<T>(ze.x - zo.y, ze.y + zo.x);
         }
-        __syncthreads();
+        block_sync();
         fft_multi<T, L, NTR, +1, 1>(reg, lds, map, twr, tr);
         C<T> *dst = reinterpret_cast<C<T> *>(a.out[g] + j * a.out_pitch);
         const T sc = a.scale;
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) dst[tr + NTR * e] = mk<T>(reg[0][e].x * sc, reg[0][e].y * sc);
-        __syncthreads();  // the next output's staging reuses this row's LDS
+        block_sync();  // the next output's staging reuses this row's LDS
     }
 }
 
@@ -350,8 +426,9 @@ template <typename T, int M> struct Dispatch {
         if constexpr (!col_var_ok<T, M, V, NF, NFAM>()) {
             return hipErrorInvalidValue;
         } else {
-            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(M / 2 + 1, 1, n), dim3(M / var_e(V)), 0, s,
-                               a, tw, ph);
+            const unsigned nblk = var_dbl(V) ? (M / 2 + 2) / 2 : M / 2 + 1;
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(nblk, 1, n), dim3(M / var_e(V)), 0, s, a,
+                               tw, ph);
             return hipGetLastError();
         }
     }
@@ -371,6 +448,8 @@ template <typename T, int M> struct Dispatch {
             case 1: return col_nf<1>(a, n, nfields, nfam, tw, ph, s);
             case 2: return col_nf<2>(a, n, nfields, nfam, tw, ph, s);
             case 3: return col_nf<3>(a, n, nfields, nfam, tw, ph, s);
+            case 4: return col_nf<4>(a, n, nfields, nfam, tw, ph, s);
+            case 6: return col_nf<6>(a, n, nfields, nfam, tw, ph, s);
         }
         return hipErrorInvalidValue;
     }
