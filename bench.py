@@ -38,6 +38,39 @@ def col_bytes(n, prec_bytes, nfields=3, nfam=1):
     return a + q + b
 
 
+# HBM traffic of the column kernel, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the same counter
+# reads for a plain copy of known size) and stored with a digest of the
+# kernel's sources; it is reported only while those sources are unchanged.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_col_uniform1024.md")
+KERNEL_SOURCES = ("fft_core.hpp", "kernels.hpp", "kernels_impl.hpp", "kernels_f32_col.hip")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2001_02765_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, n):
+    """Bytes per launch from the counter record, or None if the record is
+    missing, for another kernel or size, or older than the kernel sources."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            lines = [l for l in f if l.startswith("traffic-record: ")]
+    except OSError:
+        return None
+    for l in lines:
+        rec = json.loads(l[len("traffic-record: "):])
+        if rec.get("kernel") == kernel and rec.get("n") == n and \
+                rec.get("sources_sha256") == kernel_digest():
+            return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
+
+
 def run_precision(gl, torch, prec, n, steps, warmup, fields):
     dt = torch.float64 if prec == gl.F64 else torch.float32
     s, dx, dy, h = fields
@@ -72,6 +105,7 @@ def run_precision(gl, torch, prec, n, steps, warmup, fields):
         "ms_per_step": ms,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "stages_ms": stages,
+        "variants": list(plan.variants),
     }
 
 
@@ -264,9 +298,10 @@ def main():
 
     col_ms = r32["stages_ms"]["col"]
     achieved = col_bytes(n, 4) / (col_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": "k_col (fused column transform, FP32)",
+    kname = "grav::k_col<float, %d, %d, 3, 1>" % (2 * n, r32["variants"][1])
+    roof = {"bound": "hbm", "kernel": kname + " (fused column transform, FP32)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, n),
             "bytes_per_launch": col_bytes(n, 4), "launch_ms": col_ms}
     out = {
         "metric": "finest-cell forces/sec at 2048^2 (FP32 vs FP64 path); p50/p99 solve latency",

@@ -151,11 +151,13 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans,
                                      void *const *fy, void *workspace, void *stream);
 
 /*
- * Profiling aid: queue `reps` solves on `stream` as gravity_solve does,
- * recording HIP events on that stream between the kernels of the pipeline,
- * wait for them, and return the mean device time of each stage in
+ * Profiling aid: queue one solve on `stream` as gravity_solve does, but
+ * launch every stage (kernel) of the pipeline `reps` times back to back
+ * between two HIP events recorded on that stream, wait for them, and return
+ * the mean device time of one launch of each stage in
  * stage_ms[0 .. *nstages - 1] (at most 8 stages; names from
- * gravity_stage_name).  Outputs are those of the last solve.
+ * gravity_stage_name).  Every stage rewrites its whole output from its
+ * input, so the outputs are those of a plain solve.
  * Errors: as gravity_solve; EINVAL if reps < 1 or stage_ms/nstages is NULL.
  */
 gravity_status_t gravity_solve_profiled(gravity_plan_t plan, const void *sigma, const void *dsx,

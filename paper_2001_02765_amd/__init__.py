@@ -220,8 +220,9 @@ class Plan:
 
 
     def profile(self, sigma, dsx, dsy, fx, fy, workspace, reps=20, stream=None):
-        """Mean device milliseconds per pipeline stage over ``reps`` solves,
-        timed with HIP events on the solve stream: {stage name: ms}."""
+        """Mean device milliseconds of one launch of each pipeline stage, each
+        stage launched ``reps`` times back to back between HIP events on the
+        solve stream: {stage name: ms}."""
         ms = (ctypes.c_double * 8)()
         ns = ctypes.c_int32()
         _check(_lib.gravity_solve_profiled(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx),

@@ -408,8 +408,11 @@ bool same_group(const gravity_plan_s &a, const gravity_plan_s &b) {
 }
 
 // Queue n (1..kPack) solves of one group; ev: optional n_stages + 1 events
-// recorded between the stages.
-template <typename T> void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr) {
+// recorded between the stages.  srep > 1 (timing only) launches every stage
+// srep times back to back between its two events; each stage rewrites its
+// whole output from its input, so the repeats leave the result unchanged.
+template <typename T>
+void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, int srep = 1) {
     const gravity_plan_s &p0 = *it[0].p;
     const int nf = p0.nf, M = p0.M, H = M / 2;
     const int NF = p0.nfields;
@@ -463,10 +466,11 @@ template <typename T> void run_group(const Item *it, int n, hipStream_t s, hipEv
             ia.slopes = NF == 3;
         }
         mark();
-        hip_check(launch_inject<T>(ip, n, nf, s), "inject");
+        for (int r = 0; r < srep; ++r) hip_check(launch_inject<T>(ip, n, nf, s), "inject");
     }
     mark();
-    hip_check(launch_row_fwd<T>(rf, n, M, p0.var_rf, true, nf, NF, tw, s), "row transform");
+    for (int r = 0; r < srep; ++r)
+        hip_check(launch_row_fwd<T>(rf, n, M, p0.var_rf, true, nf, NF, tw, s), "row transform");
 
     Pack<ColArgs<T>> cp{};
     for (int i = 0; i < n; ++i) {
@@ -484,7 +488,8 @@ template <typename T> void run_group(const Item *it, int n, hipStream_t s, hipEv
         ca.out_gstride = colsz;
     }
     mark();
-    hip_check(launch_col<T>(cp, n, M, p0.var_col, NF, nfam, tw, ph, s), "column transform");
+    for (int r = 0; r < srep; ++r)
+        hip_check(launch_col<T>(cp, n, M, p0.var_col, NF, nfam, tw, ph, s), "column transform");
 
     Pack<RowInvArgs<T>> ip{};
     for (int i = 0; i < n; ++i) {
@@ -504,7 +509,8 @@ template <typename T> void run_group(const Item *it, int n, hipStream_t s, hipEv
         }
     }
     mark();
-    hip_check(launch_row_inv<T>(ip, n, M, p0.var_ri, nf, 2 * nfam, tw, s), "inverse row transform");
+    for (int r = 0; r < srep; ++r)
+        hip_check(launch_row_inv<T>(ip, n, M, p0.var_ri, nf, 2 * nfam, tw, s), "inverse row transform");
 
     if (p0.amr) {
         Pack<GatherArgs<T>> gp{};
@@ -520,7 +526,7 @@ template <typename T> void run_group(const Item *it, int n, hipStream_t s, hipEv
             maxc = std::max<int64_t>(maxc, p.ncells);
         }
         mark();
-        hip_check(launch_gather<T>(gp, n, maxc, s), "gather");
+        for (int r = 0; r < srep; ++r) hip_check(launch_gather<T>(gp, n, maxc, s), "gather");
     }
     mark();
 }
@@ -535,9 +541,9 @@ void run_items(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr) {
 // single solve entry used by the autotuner and the profiling call
 template <typename T>
 void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const void *dsy, void *fx,
-             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr, int srep = 1) {
     Item it{&p, sigma, dsx, dsy, fx, fy, ws};
-    run_group<T>(&it, 1, s, ev);
+    run_group<T>(&it, 1, s, ev, srep);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,11 +630,11 @@ template <typename T> Variants autotune(gravity_plan_s &p) {
         p.var_ri = okr ? v : best.ri;
         p.var_col = okc ? v : best.col;
         double acc[8] = {0};
-        for (int r = 0; r <= reps; ++r) {
+        for (int r = 0; r < 2; ++r) {  // warm-up, then every stage reps times back to back
             solve_t<T>(p, sg, sg + p.ncells, sg + 2 * p.ncells, out.p, (T *)out.p + p.ncells,
-                       (char *)ws.p, nullptr, ev.data());
+                       (char *)ws.p, nullptr, ev.data(), r == 0 ? 1 : reps);
             hip_check(hipEventSynchronize(ev[ns]), "hipEventSynchronize");
-            if (r == 0) continue;  // warm-up
+            if (r == 0) continue;
             for (int k = 0; k < ns; ++k) {
                 float ms = 0;
                 hip_check(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
@@ -866,21 +872,18 @@ gravity_status_t gravity_solve_profiled(gravity_plan_t p, const void *sigma, con
             e = nullptr;
             hip_check(hipEventCreate(&e), "hipEventCreate");
         }
-        std::vector<double> acc(ns, 0.0);
         hipStream_t s = (hipStream_t)stream;
-        for (int r = 0; r < reps; ++r) {
-            if (p->prec)
-                solve_t<double>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s, ev.data());
-            else
-                solve_t<float>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s, ev.data());
-            hip_check(hipEventSynchronize(ev[ns]), "hipEventSynchronize");
-            for (int k = 0; k < ns; ++k) {
-                float ms = 0;
-                hip_check(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
-                acc[k] += ms;
-            }
+        // every stage launched reps times back to back between its two events
+        if (p->prec)
+            solve_t<double>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s, ev.data(), reps);
+        else
+            solve_t<float>(*p, sigma, dsx, dsy, fx, fy, (char *)workspace, s, ev.data(), reps);
+        hip_check(hipEventSynchronize(ev[ns]), "hipEventSynchronize");
+        for (int k = 0; k < ns; ++k) {
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
+            stage_ms[k] = (double)ms / reps;
         }
-        for (int k = 0; k < ns; ++k) stage_ms[k] = acc[k] / reps;
         *nstages = ns;
     });
     for (auto &e : ev)

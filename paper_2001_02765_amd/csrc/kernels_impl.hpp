@@ -38,6 +38,16 @@ template <typename T, int M, int E, bool DBL = false> struct RowCfg {
     static_assert((RPB & (RPB - 1)) == 0, "rows per block must be a power of two");
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  The row kernels write (forward) or read (inverse) spectral columns in
+// segments of RPB consecutive rows, so adjacent row groups share cache lines;
+// this remap gives every XCD a contiguous range of row groups, so that the
+// partial lines of neighbouring groups meet in one L2.  Needs gridDim.x to be
+// a multiple of 8 (then blockIdx.x % 8 is the XCD); otherwise the identity.
+__device__ __forceinline__ int xcd_row_group(int b, int nb) {
+    return (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 // variant ids: bit 1 selects E = 16 (else 8); bit 0 selects all fields per
 // thread (rows: in sequence; columns: in lockstep) instead of one; bit 2
 // (rows only) doubles the rows per block (128-byte transposed segments).
@@ -67,7 +77,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
     __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
     const int r = t % RPB, tr = t / RPB;
-    const int64_t j = (int64_t)blockIdx.x * RPB + r;
+    const int64_t j = (int64_t)xcd_row_group(blockIdx.x, gridDim.x) * RPB + r;
     const LdsAoS map{RPB, r};
     TwReg<T, L, NTR> twr;
     twr.load(tw, 2, tr);
@@ -332,7 +342,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
     __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
     const int r = t % RPB, tr = t / RPB;
-    const int64_t j = (int64_t)blockIdx.x * RPB + r;
+    const int64_t j = (int64_t)xcd_row_group(blockIdx.x, gridDim.x) * RPB + r;
     const LdsAoS map{RPB, r};
     TwReg<T, L, NTR> twr;
     twr.load(tw, 2, tr);

@@ -265,6 +265,34 @@ def test_deterministic(gl):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_profiled_solve_equals_solve(gl):
+    """The profiling entry point repeats every stage back to back; its outputs
+    equal a plain solve's, bit for bit (uniform FP32 and AMR FP64)."""
+    n = 256
+    s, dx, dy, h = diskgen.noisy_spiral(n, 2)
+    p = gl.Plan(n, gl.F32, h0=h)
+    t = [_dev(a, "f32") for a in (s, dx, dy)]
+    fx, fy = p.solve(*t)
+    gx, gy = torch.empty_like(fx), torch.empty_like(fy)
+    st = p.profile(*t, gx, gy, p.workspace(), reps=3)
+    torch.cuda.synchronize()
+    assert set(st) == {"row_fwd", "col", "row_inv"} and all(v > 0 for v in st.values())
+    assert torch.equal(fx, gx) and torch.equal(fy, gy)
+    lay = diskgen.table10_layout()
+    rng = np.random.default_rng(4)
+    m = lay.leaf_mask()
+    fields = [np.where(m, rng.random(lay.total()) + 0.1, 0) for _ in range(3)]
+    pa = gl.Plan(lay.n0, gl.F64, x0=lay.x0, y0=lay.y0, h0=lay.h0, nlevels=lay.nlevels,
+                 patches=lay.patches)
+    ta = [_dev(a, "f64") for a in fields]
+    ax, ay = pa.solve(*ta)
+    bx, by = torch.empty_like(ax), torch.empty_like(ay)
+    st = pa.profile(*ta, bx, by, pa.workspace(), reps=2)
+    torch.cuda.synchronize()
+    assert list(st) == ["inject", "row_fwd", "col", "row_inv", "gather"]
+    assert torch.equal(ax, bx) and torch.equal(ay, by)
+
+
 def test_invalid_requests(gl):
     with pytest.raises(gl.GravityError) as e:
         gl.Plan(48, gl.F32)
