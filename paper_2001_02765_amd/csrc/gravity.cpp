@@ -667,7 +667,10 @@ void choose_variants(gravity_plan_s &p) {
         const std::string dev = device_key(p.device);
         auto key = std::make_tuple(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1);
         auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) {
+        // an entry of a tune file written by another build may name a
+        // variant this build does not have: tune again then
+        if (it != g_tuned.end() && row_variant_valid(p.prec, p.M, it->second.rf) &&
+            col_ok(p, it->second.col) && row_variant_valid(p.prec, p.M, it->second.ri)) {
             v = it->second;
         } else {
             v = p.prec ? autotune<double>(p) : autotune<float>(p);

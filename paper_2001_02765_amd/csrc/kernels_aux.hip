@@ -218,6 +218,10 @@ template <typename T, int M> static bool row_ok_t(int var) {
         case 5: return row_var_ok<T, M, 5>();
         case 6: return row_var_ok<T, M, 6>();
         case 7: return row_var_ok<T, M, 7>();
+        case 8: return row_var_ok<T, M, 8>();
+        case 9: return row_var_ok<T, M, 9>();
+        case 10: return row_var_ok<T, M, 10>();
+        case 11: return row_var_ok<T, M, 11>();
     }
     return false;
 }

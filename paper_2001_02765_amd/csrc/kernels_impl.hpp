@@ -25,15 +25,19 @@ constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
 // element), E elements per thread, RPB rows per block.  Lanes are
 // interleaved with the row index fastest, so one store instruction writes
 // RPB consecutive rows of a spectral column (transposed, coalesced output).
-template <typename T, int M, int E, bool DBL = false> struct RowCfg {
+// SC scales the rows per block: 0 the default (at most 8 FP32 / 4 FP64 rows
+// in 80 KB of LDS), 1 doubled (up to 160 KB), -1 halved (more, smaller
+// blocks for small sizes).
+template <typename T, int M, int E, int SC = 0> struct RowCfg {
     static constexpr int L = M / 2;
     static constexpr int NTR = L / E;
-    static constexpr int RMAX = (sizeof(T) == 4 ? 8 : 4) * (DBL ? 2 : 1);
+    static constexpr int RMAX = (sizeof(T) == 4 ? 8 : 4) * (SC == 1 ? 2 : 1);
     static constexpr int SLOTS = aos_slots<L>();  // LDS elements per row (AoS)
     static constexpr int BYTES = SLOTS * (int)sizeof(C<T>);
-    static constexpr int LMAX = DBL ? 163840 : 81920;
+    static constexpr int LMAX = SC == 1 ? 163840 : 81920;
     // a power of two (rows per solve are powers of two)
-    static constexpr int RPB = floor_pow2(cmax(1, cmin(RMAX, cmin(1024 / NTR, LMAX / BYTES))));
+    static constexpr int RPB0 = floor_pow2(cmax(1, cmin(RMAX, cmin(1024 / NTR, LMAX / BYTES))));
+    static constexpr int RPB = SC == -1 ? cmax(1, RPB0 / 2) : RPB0;
     static constexpr int NTH = RPB * NTR;
     static_assert((RPB & (RPB - 1)) == 0, "rows per block must be a power of two");
 };
@@ -49,17 +53,22 @@ __device__ __forceinline__ int xcd_row_group(int b, int nb) {
 }
 
 // variant ids: bit 1 selects E = 16 (else 8); bit 0 selects all fields per
-// thread (rows: in sequence; columns: in lockstep) instead of one; bit 2
-// (rows only) doubles the rows per block (128-byte transposed segments).
+// thread (rows: in sequence; columns: in lockstep) instead of one.  Row
+// kernels: bits 2-3 scale the rows per block (0 default, 1 doubled, 2
+// halved; ids 0..11).  Column kernel: bit 2 selects two columns per block
+// (ids 0..7).
 constexpr int var_e(int v) { return (v & 2) ? 16 : 8; }
 constexpr bool var_all(int v) { return (v & 1) != 0; }
 constexpr bool var_dbl(int v) { return (v & 4) != 0; }
-// a row variant exists if each row has at least 2 threads; the doubled one
-// only where it really doubles the rows per block
+constexpr int row_scale(int v) { return (v >> 2) == 1 ? 1 : ((v >> 2) == 2 ? -1 : 0); }
+// a row variant exists if each row has at least 2 threads; the doubled and
+// halved ones only where they really change the rows per block
 template <typename T, int M, int V> constexpr bool row_var_ok() {
-    if constexpr (M / 2 < 2 * var_e(V)) return false;
-    else if constexpr (var_dbl(V))
-        return RowCfg<T, M, var_e(V), true>::RPB > RowCfg<T, M, var_e(V), false>::RPB;
+    if constexpr (V >= 12 || M / 2 < 2 * var_e(V)) return false;
+    else if constexpr (row_scale(V) == 1)
+        return RowCfg<T, M, var_e(V), 1>::RPB > RowCfg<T, M, var_e(V), 0>::RPB;
+    else if constexpr (row_scale(V) == -1)
+        return RowCfg<T, M, var_e(V), -1>::RPB < RowCfg<T, M, var_e(V), 0>::RPB;
     else return true;
 }
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok();
@@ -68,11 +77,11 @@ template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok(
 // row forward: z[m] = x[2m] + i x[2m+1] -> Z = FFT_L(z) -> X[k], k in [0, L]
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V, bool PRUNED>
-__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     k_row_fwd(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
     const RowFwdArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V);
-    using CF = RowCfg<T, M, E, var_dbl(V)>;
+    using CF = RowCfg<T, M, E, row_scale(V)>;
     constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
     __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
@@ -177,7 +186,7 @@ template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok() {
-    if constexpr (V >= 4 && (V == 5 || V == 7 || M < 512)) return false;
+    if constexpr (V >= 8 || (V >= 4 && (V == 5 || V == 7 || M < 512))) return false;
     else if constexpr (V >= 4) return M >= 2 * var_e(V) && 2 * soa_region<M>() * (int)sizeof(C<T>) <= 163840;
     else if constexpr (NF == 1 && V != 0) return false;
     else if constexpr (M <= 256 && V > 1) return false;
@@ -333,11 +342,11 @@ __global__ void __launch_bounds__((M / var_e(V)))
 // row inverse: Y[k], k in [0, L] (Hermitian half) -> y[n], n < M/2, scaled
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V>
-__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), var_dbl(V)>::NTH))
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     k_row_inv(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
     const RowInvArgs<T> &a = pk.a[blockIdx.z];
     constexpr int E = var_e(V);
-    using CF = RowCfg<T, M, E, var_dbl(V)>;
+    using CF = RowCfg<T, M, E, row_scale(V)>;
     constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
     __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
@@ -406,7 +415,7 @@ template <typename T, int M> struct Dispatch {
         if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
         } else {
-            using CF = RowCfg<T, M, var_e(V), var_dbl(V)>;
+            using CF = RowCfg<T, M, var_e(V), row_scale(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
             dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields, n);
             if (pruned)
@@ -427,6 +436,10 @@ template <typename T, int M> struct Dispatch {
             case 5: return row_fwd_v<5>(a, n, pruned, nrows, nfields, tw, s);
             case 6: return row_fwd_v<6>(a, n, pruned, nrows, nfields, tw, s);
             case 7: return row_fwd_v<7>(a, n, pruned, nrows, nfields, tw, s);
+            case 8: return row_fwd_v<8>(a, n, pruned, nrows, nfields, tw, s);
+            case 9: return row_fwd_v<9>(a, n, pruned, nrows, nfields, tw, s);
+            case 10: return row_fwd_v<10>(a, n, pruned, nrows, nfields, tw, s);
+            case 11: return row_fwd_v<11>(a, n, pruned, nrows, nfields, tw, s);
         }
         return hipErrorInvalidValue;
     }
@@ -469,7 +482,7 @@ template <typename T, int M> struct Dispatch {
         if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
         } else {
-            using CF = RowCfg<T, M, var_e(V), var_dbl(V)>;
+            using CF = RowCfg<T, M, var_e(V), row_scale(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
             dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nout, n);
             hipLaunchKernelGGL((k_row_inv<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
@@ -487,6 +500,10 @@ template <typename T, int M> struct Dispatch {
             case 5: return row_inv_v<5>(a, n, nrows, nout, tw, s);
             case 6: return row_inv_v<6>(a, n, nrows, nout, tw, s);
             case 7: return row_inv_v<7>(a, n, nrows, nout, tw, s);
+            case 8: return row_inv_v<8>(a, n, nrows, nout, tw, s);
+            case 9: return row_inv_v<9>(a, n, nrows, nout, tw, s);
+            case 10: return row_inv_v<10>(a, n, nrows, nout, tw, s);
+            case 11: return row_inv_v<11>(a, n, nrows, nout, tw, s);
         }
         return hipErrorInvalidValue;
     }
