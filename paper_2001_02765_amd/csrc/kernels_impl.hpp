@@ -13,6 +13,8 @@
 // lockstep); the plan's autotuner times them and keeps the fastest.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace grav {
@@ -178,16 +180,22 @@ __device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, co
     }
 }
 
+// Column exchanges use the swizzled map up to M = 4096 (measured faster);
+// the largest transforms, whose 1024-thread blocks are short of registers,
+// keep the padded map's cheaper addresses.
+template <int M> using ColMap = std::conditional_t<(M <= 4096), LdsSwz, LdsSoA>;
+template <int M> constexpr int col_region() { return ColMap<M>::template region<M>(); }
+
 template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
     static constexpr int NB = var_all(V) ? cmax(NF, 2 * NFAM) : 1;
-    static constexpr int N = NB * soa_region<M>();
+    static constexpr int N = NB * col_region<M>();
 };
 // a column variant exists if its transform has at least 2 threads and its
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok() {
     if constexpr (V >= 8 || (V >= 4 && (V == 5 || V == 7 || M < 512))) return false;
-    else if constexpr (V >= 4) return M >= 2 * var_e(V) && 2 * soa_region<M>() * (int)sizeof(C<T>) <= 163840;
+    else if constexpr (V >= 4) return M >= 2 * var_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
     else if constexpr (NF == 1 && V != 0) return false;
     else if constexpr (M <= 256 && V > 1) return false;
     else return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>) <= 163840;
@@ -197,7 +205,7 @@ template <typename T, int M, int V, int NF, int NFAM>
 __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                          const C<T> *__restrict__ ph) {
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
-    const LdsSoA map{soa_region<M>()};
+    const ColMap<M> map{col_region<M>()};
     __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM>::N];
     const int t = threadIdx.x;
     const int kx = blockIdx.x;
@@ -267,8 +275,8 @@ template <typename T, int M, int V, int NF, int NFAM>
 __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                           const C<T> *__restrict__ ph) {
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
-    const LdsSoA map{soa_region<M>()};
-    __shared__ C<T> lds[2 * soa_region<M>()];
+    const ColMap<M> map{col_region<M>()};
+    __shared__ C<T> lds[2 * col_region<M>()];
     const int t = threadIdx.x;
     const int kx0 = 2 * blockIdx.x;
     const bool has1 = kx0 + 1 <= H;
@@ -329,8 +337,21 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
     }
 }
 
+// Occupancy target of the FP32 lockstep column variant: as many waves per
+// SIMD as its LDS allows (three 48 KB blocks per CU at M = 2048), so that the
+// register allocation stays within the matching budget.
+template <typename T, int M, int V, int NF, int NFAM> constexpr int col_waves() {
+    if constexpr (sizeof(T) == 4 && V == 1 && NFAM == 1) {
+        constexpr int blocks = 163840 / (ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>));
+        constexpr int waves = blocks * (M / var_e(V)) / 256;
+        return cmax(1, cmin(3, waves));
+    } else {
+        return 1;
+    }
+}
+
 template <typename T, int M, int V, int NF, int NFAM>
-__global__ void __launch_bounds__((M / var_e(V)))
+__global__ void __launch_bounds__((M / var_e(V)), (col_waves<T, M, V, NF, NFAM>()))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
     if constexpr (var_dbl(V))
         col2_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
