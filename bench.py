@@ -27,14 +27,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 def col_bytes(n, prec_bytes, nfields=3, nfam=1):
     """Algorithmic bytes of one column-kernel launch (uniform or AMR solve):
-    read the row spectra of every input field, read every kernel-spectrum
-    quadrant once, write the column-inverted force spectra."""
+    read the n-row spectra of every input field at the M/2 odd x frequencies
+    (M = 2n), read every kernel spectrum (M/2 x (M/2 + 1) reals per kind)
+    once, write the column-inverted force spectra."""
     m = 2 * n
-    h1 = m // 2 + 1
+    cols = m // 2
     cplx = 2 * prec_bytes
-    a = nfields * h1 * n * cplx
-    q = nfam * 6 * h1 * h1 * prec_bytes
-    b = 2 * nfam * h1 * n * cplx
+    a = nfields * cols * n * cplx
+    q = nfam * 6 * cols * (m // 2 + 1) * prec_bytes
+    b = 2 * nfam * cols * n * cplx
     return a + q + b
 
 

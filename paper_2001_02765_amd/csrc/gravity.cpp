@@ -124,20 +124,25 @@ struct Twiddles {
     DevBuf tw, ph;
 };
 
+// tw: exp(-2 pi i k / M) for k in [0, M), then the half-bin factors
+//     exp(-i pi (2k + 1) / M) for k in [0, M/2) of the odd-frequency row
+//     transforms.
+// ph: exp(-i pi k / M) for k in [0, M/2] (corner phase of a y frequency),
+//     then exp(-i pi (k + 1/2) / M) for k in [0, M/2) (corner phase of the
+//     odd x frequency k + 1/2).
 template <typename T> void fill_twiddles(int M, std::vector<T> &tw, std::vector<T> &ph) {
     const long double pi = 3.141592653589793238462643383279502884L;
-    tw.resize(2 * (size_t)M);
-    ph.resize(2 * (size_t)(M / 2 + 1));
-    for (int k = 0; k < M; ++k) {
-        long double a = 2 * pi * k / M;
-        tw[2 * k] = (T)cosl(a);
-        tw[2 * k + 1] = (T)(-sinl(a));
-    }
-    for (int k = 0; k <= M / 2; ++k) {
-        long double a = pi * k / M;
-        ph[2 * k] = (T)cosl(a);
-        ph[2 * k + 1] = (T)(-sinl(a));
-    }
+    const int H = M / 2;
+    tw.resize(2 * (size_t)(M + H));
+    ph.resize(2 * (size_t)(H + 1 + H));
+    auto put = [](std::vector<T> &v, size_t i, long double a) {
+        v[2 * i] = (T)cosl(a);
+        v[2 * i + 1] = (T)(-sinl(a));
+    };
+    for (int k = 0; k < M; ++k) put(tw, k, 2 * pi * k / M);
+    for (int k = 0; k < H; ++k) put(tw, M + k, pi * (2 * k + 1) / M);
+    for (int k = 0; k <= H; ++k) put(ph, k, pi * k / M);
+    for (int k = 0; k < H; ++k) put(ph, H + 1 + k, pi * (k + 0.5L) / M);
 }
 
 std::shared_ptr<Twiddles> make_twiddles(int device, int M, int prec) {
@@ -146,8 +151,8 @@ std::shared_ptr<Twiddles> make_twiddles(int device, int M, int prec) {
     t->M = M;
     t->prec = prec;
     size_t esz = prec ? sizeof(double) : sizeof(float);
-    t->tw.alloc(2 * esz * M, "twiddle table");
-    t->ph.alloc(2 * esz * (M / 2 + 1), "phase table");
+    t->tw.alloc(2 * esz * (M + M / 2), "twiddle table");
+    t->ph.alloc(2 * esz * (M + 1), "phase table");
     if (prec) {
         std::vector<double> tw, ph;
         fill_twiddles<double>(M, tw, ph);
@@ -162,7 +167,9 @@ std::shared_ptr<Twiddles> make_twiddles(int device, int M, int prec) {
     return t;
 }
 
-// six kernel-spectrum quadrants of one family at one size and precision
+// six kernel spectra of one family at one size and precision: per kind the
+// odd x frequencies kx + 1/2, kx in [0, M/2), by the y frequencies ky in
+// [0, M/2] (a half plane; negative ky follow from the kind's parity in y)
 struct KernelSet {
     int device, M, prec, family;
     DevBuf q;
@@ -192,12 +199,12 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
     ks->family = family;
     const int H = M / 2;
     ks->q_pitch = ((H + 1) + 63) / 64 * 64;
-    ks->q_kstride = ks->q_pitch * (H + 1);
+    ks->q_kstride = ks->q_pitch * H;
     const size_t esz = prec ? sizeof(double) : sizeof(float);
     ks->q.alloc(6 * esz * ks->q_kstride, "kernel spectra");
     // transient double-precision buffers
     DevBuf table(sizeof(double) * (size_t)M * M, "kernel table");
-    DevBuf rows(sizeof(double) * 2 * (size_t)(H + 1) * M, "kernel table row spectra");
+    DevBuf rows(sizeof(double) * 2 * (size_t)H * M, "kernel table row spectra");
     auto tw64 = get_twiddles(device, M, 1);
     TableArgs ta{};
     ta.out = (double *)table.p;
@@ -419,7 +426,7 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
     const int nfam = p0.amr ? 2 : 1;
     const C<T> *tw = (const C<T> *)p0.tw->tw.p;
     const C<T> *ph = (const C<T> *)p0.tw->ph.p;
-    const int64_t colsz = (int64_t)(H + 1) * nf;
+    const int64_t colsz = (int64_t)H * nf;  // M/2 spectral columns of nf rows
     const int64_t n2 = (int64_t)nf * nf;
     int stage = 0;
     auto mark = [&]() {
@@ -741,7 +748,7 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         }
         const size_t esz = p->prec ? sizeof(double) : sizeof(float);
         const int64_t n = p->nf, H = p->M / 2;
-        const size_t colsz = 2 * esz * (size_t)((H + 1) * n);
+        const size_t colsz = 2 * esz * (size_t)(H * n);
         size_t off = 0;
         if (p->amr) {
             p->off_w = off;

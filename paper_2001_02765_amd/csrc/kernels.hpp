@@ -1,8 +1,9 @@
 // Kernel argument blocks and host launchers shared by the HIP kernels and
 // the host runtime.  Layouts (all device memory):
 //   fields   : n x n row-major real arrays (row = y index, x fastest)
-//   A        : forward row spectra, A[f][kx][j], kx in [0, M/2], j in [0, rows)
-//   Q        : kernel-spectrum quadrants, Q[kind][kx][ky], kx, ky in [0, M/2]
+//   A        : forward row spectra at the odd x frequencies kx + 1/2,
+//              A[f][kx][j], kx in [0, M/2), j in [0, rows)
+//   Q        : kernel spectra, Q[kind][kx][ky], kx in [0, M/2), ky in [0, M/2]
 //   B        : column-inverted spectra, B[g][kx][j]
 // M is the zero-padded transform size (2 n), n the lattice cells per side.
 #pragma once
@@ -30,7 +31,7 @@ template <typename T> struct RowFwdArgs {
 template <typename T> struct ColArgs {
     const C<T> *in;  // A
     int64_t in_pitch, in_fstride;
-    const T *q[2];   // quadrants of the centre / corner family: kind k at q[f] + k q_kstride
+    const T *q[2];   // spectra of the centre / corner family: kind k at q[f] + k q_kstride
     int64_t q_pitch, q_kstride;
     C<T> *out;       // B
     int64_t out_pitch, out_gstride;

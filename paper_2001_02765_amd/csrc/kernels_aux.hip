@@ -88,10 +88,13 @@ __device__ double quad_kernel(int kind, double uc, double vc, const TableArgs &a
     return 0.25 * sum;
 }
 
-// Circulant table c[m] = K(-m): entry (my, mx) holds the kernel of the source
-// cell at offset d = -(signed m) from the target.  Family 0 (cell-centre
-// targets): cell [d - 1/2, d + 1/2], |d| <= M/2 - 1, the rest zero.
-// Family 1 (targets on lattice corners): cell [d, d + 1], d in [-M/2, M/2 - 1].
+// Table c[m] = K(-m): entry (my, mx) holds the kernel of the source cell at
+// offset d = -(signed m) from the target.  Family 0 (cell-centre targets):
+// cell [d - 1/2, d + 1/2], |d| <= M/2 - 1, the rest zero.  Family 1 (targets
+// on lattice corners): cell [d, d + 1], d in [-M/2, M/2 - 1].  Circulant in
+// y; negacyclic in x (entries of negative signed mx, mx > M/2, negated), the
+// embedding whose odd-frequency transform turns the product of spectra into
+// the same linear convolution.
 __global__ void __launch_bounds__(256) k_ktable(TableArgs a) {
     const int64_t total = (int64_t)a.M * a.M;
     const int H = a.M / 2;
@@ -121,7 +124,7 @@ __global__ void __launch_bounds__(256) k_ktable(TableArgs a) {
                 val = closed_kernel(a.kind, uc, vc, t0zero);
             }
         }
-        a.out[q] = val;
+        a.out[q] = mx > H ? -val : val;
     }
 }
 
@@ -144,7 +147,7 @@ __global__ void __launch_bounds__((ExtractCfg<M>::NT))
         const int ky = t + NT * e;
         if (ky <= H) {
             C<double> v = reg[e];
-            if (corner) v = cmulc<double>(v, cmul<double>(ph[kx], ph[ky]));
+            if (corner) v = cmulc<double>(v, cmul<double>(ph[H + 1 + kx], ph[ky]));
             dst[ky] = (TQ)(imag ? v.y : v.x);
         }
     }
@@ -203,7 +206,7 @@ template <typename T> __global__ void __launch_bounds__(256) k_gather(Pack<Gathe
 template <typename TQ, int M>
 static hipError_t col_extract_m(const C<double> *in, TQ *q, int64_t q_pitch, int imag, int corner,
                                 const C<double> *tw, const C<double> *ph, hipStream_t s) {
-    hipLaunchKernelGGL((k_col_extract<TQ, M>), dim3(M / 2 + 1), dim3(ExtractCfg<M>::NT), 0, s, in, q,
+    hipLaunchKernelGGL((k_col_extract<TQ, M>), dim3(M / 2), dim3(ExtractCfg<M>::NT), 0, s, in, q,
                        q_pitch, imag, corner, tw, ph);
     return hipGetLastError();
 }

@@ -76,7 +76,12 @@ template <typename T, int M, int V> constexpr bool row_var_ok() {
 template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok();
 
 // ---------------------------------------------------------------------------
-// row forward: z[m] = x[2m] + i x[2m+1] -> Z = FFT_L(z) -> X[k], k in [0, L]
+// row forward, odd frequencies: X(k + 1/2) = sum_n x[n] exp(-2 pi i n (k+1/2)/M)
+// for k in [0, M/2).  z[m] = (x[2m] + i x[2m+1]) exp(-2 pi i m/M) -> Z =
+// FFT_L(z); with Zn = Z[L-1-k]: X(k+1/2) = (Z[k] + conj Zn)/2
+// + exp(-i pi (2k+1)/M) (Z[k] - conj Zn)/(2i).  A real row has exactly M/2
+// independent odd-frequency bins (X(M-1-k+1/2) = conj X(k+1/2)), all
+// complex, so there is no separate real Nyquist bin.
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V, bool PRUNED>
 __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
@@ -90,6 +95,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     const int r = t % RPB, tr = t / RPB;
     const int64_t j = (int64_t)xcd_row_group(blockIdx.x, gridDim.x) * RPB + r;
     const LdsAoS map{RPB, r};
+    const C<T> *__restrict__ hw = tw + M;  // exp(-i pi (2k+1)/M)
     TwReg<T, L, NTR> twr;
     twr.load(tw, 2, tr);
 
@@ -104,8 +110,9 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
             if (PRUNED && e >= E / 2) {
                 reg[0][e] = mk<T>(0, 0);
             } else {
-                C<T> v = row[tr + NTR * e];
-                reg[0][e] = mk<T>(v.x * sc, v.y * sc);
+                const int m = tr + NTR * e;
+                const C<T> v = row[m];
+                reg[0][e] = cmul<T>(mk<T>(v.x * sc, v.y * sc), tw[m]);
             }
         }
         fft_multi<T, L, NTR, -1, 1>(reg, lds, map, twr, tr);
@@ -117,14 +124,13 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
         for (int e = 0; e < E; ++e) {
             const int k = tr + NTR * e;
             const C<T> zk = reg[0][e];
-            const C<T> zn = lds[map.at(0, (L - k) & (L - 1))];
-            const C<T> w = tw[k];
+            const C<T> zn = lds[map.at(0, L - 1 - k)];
+            const C<T> w = hw[k];
             const T px = zk.x + zn.x, py = zk.y - zn.y;
             const T qx = zk.x - zn.x, qy = zk.y + zn.y;
             dst[(int64_t)k * a.out_pitch] =
                 mk<T>((T)0.5 * (px + w.x * qy + w.y * qx), (T)0.5 * (py - w.x * qx + w.y * qy));
         }
-        if (tr == 0) dst[(int64_t)L * a.out_pitch] = mk<T>(reg[0][0].x - reg[0][0].y, (T)0);
         block_sync();  // the next field's first pass reuses this row's LDS
     }
 }
@@ -134,11 +140,12 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
 // column, product with the kernel spectra of both force components, then
 // inverse transforms of the accumulated force spectra.
 //
-// Kernel spectra are stored as one real quadrant per kind (ky in [0, M/2]):
-// kinds {x0, y0} are purely imaginary, the others real; a negative ky takes
-// the kind's parity in y.  Corner-family spectra carry the phase
-// exp(-i pi (kx + ky)/M) (targets half a cell from the source lattice),
-// applied once to the accumulated sums.
+// Column kx holds the odd x frequency kx + 1/2, kx in [0, M/2).  Kernel
+// spectra are stored as one real half plane per kind (all M/2 columns, ky in
+// [0, M/2]): kinds {x0, y0} are purely imaginary, the others real; a negative
+// ky takes the kind's parity in y.  Corner-family spectra carry the phase
+// exp(-i pi (kx + 1/2 + ky)/M) (targets half a cell from the source
+// lattice), applied once to the accumulated sums.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int parity_y(int kind) {
     // x0 even, xx even, xy odd, y0 odd, yx odd, yy even (in y)
@@ -241,7 +248,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
         }
     }
     if constexpr (NFAM == 2) {
-        const C<T> px = ph[kx];
+        const C<T> px = ph[H + 1 + kx];  // exp(-i pi (kx + 1/2)/M)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int ky = t + NT * e;
@@ -267,10 +274,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 
 // Two adjacent columns per block (variants 4, 6): the fields are taken one
 // after the other, but each transform runs for both columns in lockstep, so
-// the twiddle registers serve two columns and (M/2+1)/2 blocks of 34 KB LDS
-// (FP32, M = 2048) run in a single dispatch round.  The last block of an odd
-// column count carries a zero dummy column (uniform control flow for the
-// block barriers, nothing loaded or stored for it).
+// the twiddle registers serve two columns and M/4 blocks (512 blocks of 32 KB
+// LDS at M = 2048 FP32: two per CU) run in a single dispatch round.
 template <typename T, int M, int V, int NF, int NFAM>
 __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                           const C<T> *__restrict__ ph) {
@@ -279,7 +284,6 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
     __shared__ C<T> lds[2 * col_region<M>()];
     const int t = threadIdx.x;
     const int kx0 = 2 * blockIdx.x;
-    const bool has1 = kx0 + 1 <= H;
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
 
@@ -296,19 +300,18 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
         C<T> x[2][E];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const bool ok = c == 0 || has1;
             const C<T> *src = a.in + f * a.in_fstride + (int64_t)(kx0 + c) * a.in_pitch;
 #pragma unroll
-            for (int e = 0; e < E; ++e) x[c][e] = (ok && e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
+            for (int e = 0; e < E; ++e) x[c][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
         }
         fft_multi<T, M, NT, -1, 2>(x, lds, map, twr, t);
         col_mac<T, M, E, NFAM>(acc[0], x[0], f, a, kx0, t);
-        if (has1) col_mac<T, M, E, NFAM>(acc[1], x[1], f, a, kx0 + 1, t);
+        col_mac<T, M, E, NFAM>(acc[1], x[1], f, a, kx0 + 1, t);
     }
     if constexpr (NFAM == 2) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const C<T> px = ph[(kx0 + c) <= H ? kx0 + c : H];
+            const C<T> px = ph[H + 1 + kx0 + c];  // exp(-i pi (kx + 1/2)/M)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int ky = t + NT * e;
@@ -329,7 +332,6 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
         fft_multi<T, M, NT, +1, 2>(y, lds, map, twr, t);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            if (c == 1 && !has1) break;
             C<T> *dst = a.out + g * a.out_gstride + (int64_t)(kx0 + c) * a.out_pitch;
 #pragma unroll
             for (int e = 0; e < E / 2; ++e) dst[t + NT * e] = y[c][e];
@@ -360,7 +362,11 @@ __global__ void __launch_bounds__((M / var_e(V)), (col_waves<T, M, V, NF, NFAM>(
 }
 
 // ---------------------------------------------------------------------------
-// row inverse: Y[k], k in [0, L] (Hermitian half) -> y[n], n < M/2, scaled
+// row inverse, odd frequencies: Y(k + 1/2), k in [0, L) (the independent
+// half of a real row's spectrum) -> y[n] = sum over all M odd frequencies of
+// Y exp(+2 pi i n (k+1/2)/M), n < M/2, scaled.  With Yn = Y[L-1-k]:
+// Z[k] = (Y[k] + conj Yn) + i exp(+i pi (2k+1)/M) (Y[k] - conj Yn),
+// z = IFFT_L(Z) (unnormalised), y[2m] + i y[2m+1] = z[m] exp(+2 pi i m/M).
 // ---------------------------------------------------------------------------
 template <typename T, int M, int V>
 __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
@@ -374,6 +380,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     const int r = t % RPB, tr = t / RPB;
     const int64_t j = (int64_t)xcd_row_group(blockIdx.x, gridDim.x) * RPB + r;
     const LdsAoS map{RPB, r};
+    const C<T> *__restrict__ hw = tw + M;  // exp(-i pi (2k+1)/M)
     TwReg<T, L, NTR> twr;
     twr.load(tw, 2, tr);
 
@@ -386,20 +393,15 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
             const int k = tr + NTR * e;
             lds[map.at(0, k)] = src[(int64_t)k * a.in_pitch];
         }
-        if (tr == 0) lds[map.at(0, L)] = src[(int64_t)L * a.in_pitch];
         block_sync();
         C<T> reg[1][E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = tr + NTR * e;
-            C<T> yk = lds[map.at(0, k)];
-            C<T> yn = lds[map.at(0, L - k)];
-            if (k == 0) {  // Y[0] and Y[L] of a real signal are real
-                yk.y = 0;
-                yn.y = 0;
-            }
+            const C<T> yk = lds[map.at(0, k)];
+            const C<T> yn = lds[map.at(0, L - 1 - k)];
             const C<T> ze = mk<T>(yk.x + yn.x, yk.y - yn.y);
-            const C<T> zo = cmulc<T>(mk<T>(yk.x - yn.x, yk.y + yn.y), tw[k]);
+            const C<T> zo = cmulc<T>(mk<T>(yk.x - yn.x, yk.y + yn.y), hw[k]);
             reg[0][e] = mk<T>(ze.x - zo.y, ze.y + zo.x);
         }
         block_sync();
@@ -407,7 +409,11 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
         C<T> *dst = reinterpret_cast<C<T> *>(a.out[g] + j * a.out_pitch);
         const T sc = a.scale;
 #pragma unroll
-        for (int e = 0; e < E / 2; ++e) dst[tr + NTR * e] = mk<T>(reg[0][e].x * sc, reg[0][e].y * sc);
+        for (int e = 0; e < E / 2; ++e) {
+            const int m = tr + NTR * e;
+            const C<T> z = cmulc<T>(reg[0][e], tw[m]);
+            dst[m] = mk<T>(z.x * sc, z.y * sc);
+        }
         block_sync();  // the next output's staging reuses this row's LDS
     }
 }
@@ -470,7 +476,7 @@ template <typename T, int M> struct Dispatch {
         if constexpr (!col_var_ok<T, M, V, NF, NFAM>()) {
             return hipErrorInvalidValue;
         } else {
-            const unsigned nblk = var_dbl(V) ? (M / 2 + 2) / 2 : M / 2 + 1;
+            const unsigned nblk = var_dbl(V) ? M / 4 : M / 2;
             hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(nblk, 1, n), dim3(M / var_e(V)), 0, s, a,
                                tw, ph);
             return hipGetLastError();
