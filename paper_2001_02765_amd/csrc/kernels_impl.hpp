@@ -339,21 +339,8 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
     }
 }
 
-// Occupancy target of the FP32 lockstep column variant: as many waves per
-// SIMD as its LDS allows (three 48 KB blocks per CU at M = 2048), so that the
-// register allocation stays within the matching budget.
-template <typename T, int M, int V, int NF, int NFAM> constexpr int col_waves() {
-    if constexpr (sizeof(T) == 4 && V == 1 && NFAM == 1) {
-        constexpr int blocks = 163840 / (ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>));
-        constexpr int waves = blocks * (M / var_e(V)) / 256;
-        return cmax(1, cmin(3, waves));
-    } else {
-        return 1;
-    }
-}
-
 template <typename T, int M, int V, int NF, int NFAM>
-__global__ void __launch_bounds__((M / var_e(V)), (col_waves<T, M, V, NF, NFAM>()))
+__global__ void __launch_bounds__((M / var_e(V)))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
     if constexpr (var_dbl(V))
         col2_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
