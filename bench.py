@@ -240,9 +240,34 @@ def cpu_baseline(n, fields, budget_s=15.0):
     t0 = timed(k0)
     k = int(max(k0, min(4096, k0 * budget_s / max(t0, 1e-3))))
     el = timed(k)
+    # one core, as the paper's Fortran baseline ran: a few targets
+    tg1 = rng.choice(n * n, 4, replace=False)
+    t1 = time.perf_counter()
+    oracle.direct(lay_rect, s.ravel(), dx.ravel(), dy.ravel(), cent[tg1], threads=1)
+    el1 = time.perf_counter() - t1
     return {"value": k / el, "unit": "forces/s", "cores": threads, "kind": "oracle",
             "sample": "%d seeded target cells of the %dx%d disk, each summed over all %d source "
-                      "cells with the exact kernels (direct method), %.1f s" % (k, n, n, n * n, el)}
+                      "cells with the exact kernels (direct method), %.1f s" % (k, n, n, n * n, el),
+            "value_1core": 4 / el1, "sample_1core": "4 target cells on one thread, %.1f s" % el1}
+
+
+def copy_gbs(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes / s) of a 1 GiB buffer:
+    the bandwidth a plain streaming kernel reaches on this GPU."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def _uniform_rects(n, h):
@@ -303,7 +328,8 @@ def main():
     roof = {"bound": "hbm", "kernel": kname + " (fused column transform, FP32)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, n),
-            "bytes_per_launch": col_bytes(n, 4), "launch_ms": col_ms}
+            "bytes_per_launch": col_bytes(n, 4), "launch_ms": col_ms,
+            "copy_gbs": copy_gbs(torch)}
     out = {
         "metric": "finest-cell forces/sec at 2048^2 (FP32 vs FP64 path); p50/p99 solve latency",
         "value": r32["value"],
