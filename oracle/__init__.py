@@ -37,6 +37,11 @@ def _load():
                                        ctypes.c_double, dp, dp, dp, ctypes.c_double,
                                        ctypes.c_int64, i64p, dp, dp, ctypes.c_int]
         lib.oracle_uniform.restype = ctypes.c_int
+        lib.oracle_cell_kernels_z.argtypes = [ctypes.c_double] * 7 + [dp]
+        lib.oracle_cell_kernels_z.restype = ctypes.c_int
+        lib.oracle_direct_z.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, dp,
+                                        ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
+        lib.oracle_direct_z.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -90,6 +95,38 @@ def direct(rect, sigma, dsx, dsy, targets, G=1.0, threads=0):
     if rc != 0:
         raise ValueError("a target lies on a source boundary")
     return fx, fy
+
+
+def cell_kernels_z(xt, yt, z, xl, xr, yd, yu):
+    """Nine exact kernels of one source rectangle at a target at height z != 0
+    above the disk plane (Section 2 at general z).
+
+    Returns (Kx0, Kxx, Kxy, Ky0, Kyx, Kyy, Kz0, Kzx, Kzy).
+    """
+    out = np.zeros(9)
+    rc = _load().oracle_cell_kernels_z(float(xt), float(yt), float(z), float(xl), float(xr),
+                                       float(yd), float(yu), _dp(out))
+    if rc != 0:
+        raise ValueError("z must be finite and non-zero")
+    return out
+
+
+def direct_z(rect, sigma, dsx, dsy, targets, z, G=1.0, threads=0):
+    """Direct sum at targets at height z != 0 above the disk: (fx, fy, fz)."""
+    rect = _f64(rect).reshape(-1, 4)
+    n = rect.shape[0]
+    sigma = _f64(sigma).reshape(n)
+    dsx = None if dsx is None else _f64(dsx).reshape(n)
+    dsy = None if dsy is None else _f64(dsy).reshape(n)
+    targets = _f64(targets).reshape(-1, 2)
+    m = targets.shape[0]
+    fx, fy, fz = np.zeros(m), np.zeros(m), np.zeros(m)
+    rc = _load().oracle_direct_z(n, _dp(rect), _dp(sigma), _dp(dsx), _dp(dsy), m,
+                                 _dp(targets), float(z), float(G), _dp(fx), _dp(fy), _dp(fz),
+                                 int(threads))
+    if rc != 0:
+        raise ValueError("z must be finite and non-zero")
+    return fx, fy, fz
 
 
 def uniform(sigma, dsx, dsy, x0, y0, h, G=1.0, targets=None, threads=0):

@@ -6,7 +6,9 @@
   superposition.
 * Kuzmin disk: s = M a / (2 pi (r^2 + a^2)^{3/2}), radial force
   -G M r / (r^2 + a^2)^{3/2}; on a finite square the force of the mass outside
-  the square is removed by quadrature (``kuzmin_exterior_force``).
+  the square is removed by quadrature (``kuzmin_exterior_force``).  Above the
+  plane the disk's potential is that of a point mass at depth a below the
+  target's side, -G M / sqrt(r^2 + (a + |z|)^2) (``kuzmin_force_z``).
 * Area-weighted error norms of Section 3.
 """
 import numpy as np
@@ -149,6 +151,58 @@ def kuzmin_truncated_force(X, Y, M=1.0, a=0.2, G=1.0, half=1.0):
     fx = np.where(swap, ty, tx) * np.sign(X)
     fy = np.where(swap, tx, ty) * np.sign(Y)
     return fx, fy
+
+
+def kuzmin_force_z(X, Y, z, M=1.0, a=0.2, G=1.0):
+    """Force at height z of the untruncated Kuzmin disk, whose potential above
+    the plane is -G M / sqrt(r^2 + (a + |z|)^2): returns (Fx, Fy, Fz)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    b = a + abs(z)
+    q = (X * X + Y * Y + b * b) ** 1.5
+    return -G * M * X / q, -G * M * Y / q, -G * M * np.sign(z) * b / q
+
+
+def _rect_force_z(xt, yt, z, xa, xb, ya, yb, sig, G, npts=12):
+    """(Fx, Fy, Fz) at (xt, yt, z) of density sig over [xa,xb]x[ya,yb] in the
+    plane, by tensor Gauss-Legendre on panels graded towards the target's foot."""
+    dist = max(xa - xt, xt - xb, ya - yt, yt - yb, 0.0)
+    d0 = max(dist, abs(z), 1e-6) * 0.5
+    bx = _graded_breaks(xa, xb, xt, d0)
+    by = _graded_breaks(ya, yb, yt, d0)
+    g, w = _gl(npts)
+    ax = 0.5 * (bx[1:] - bx[:-1])
+    cx = 0.5 * (bx[1:] + bx[:-1])
+    xs = (cx[:, None] + ax[:, None] * g[None, :]).ravel()
+    wx = (ax[:, None] * w[None, :]).ravel()
+    ay = 0.5 * (by[1:] - by[:-1])
+    cy = 0.5 * (by[1:] + by[:-1])
+    ys = (cy[:, None] + ay[:, None] * g[None, :]).ravel()
+    wy = (ay[:, None] * w[None, :]).ravel()
+    U = xs[None, :] - xt
+    V = ys[:, None] - yt
+    r3 = (U * U + V * V + z * z) ** 1.5
+    S = sig(xs[None, :], ys[:, None]) * wy[:, None] * wx[None, :]
+    return G * np.sum(S * U / r3), G * np.sum(S * V / r3), G * np.sum(S * (-z) / r3)
+
+
+def kuzmin_truncated_force_z(X, Y, z, M=1.0, a=0.2, G=1.0, half=1.0, far=60.0):
+    """Force at height z of the Kuzmin density restricted to [-half, half]^2:
+    the analytic force minus that of the mass outside the square (out to
+    |x|, |y| <= far), at each target (X, Y) in the square."""
+    sig = lambda x, y: kuzmin_sigma(x, y, M, a)
+    strips = [(-far, far, half, far), (-far, far, -far, -half),
+              (-far, -half, -half, half), (half, far, -half, half)]
+    X = np.asarray(X, dtype=np.float64).ravel()
+    Y = np.asarray(Y, dtype=np.float64).ravel()
+    kx, ky, kz = kuzmin_force_z(X, Y, z, M, a, G)
+    out = [kx.copy(), ky.copy(), kz.copy()]
+    for i in range(X.size):
+        for (xa, xb, ya, yb) in strips:
+            g = _rect_force_z(X[i], Y[i], z, xa, xb, ya, yb, sig, G)
+            for c in range(3):
+                out[c][i] -= g[c]
+    return tuple(out)
 
 
 def norms(err, area):

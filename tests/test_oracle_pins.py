@@ -316,3 +316,115 @@ def test_amr_layout_invariance_table10():
     sc = np.max(np.abs(ux))
     np.testing.assert_allclose(fx[keep], ux[idx[keep]], rtol=0, atol=1e-13 * sc)
     np.testing.assert_allclose(fy[keep], uy[idx[keep]], rtol=0, atol=1e-13 * sc)
+
+
+# ---------------------------------------------------------------------------
+# off-plane targets (Section 2 at z != 0)
+# ---------------------------------------------------------------------------
+
+def quad_kernels_z(xt, yt, z, xl, xr, yd, yu, npts=24):
+    """Composite Gauss-Legendre integration of the nine defining integrands at
+    height z over the source rectangle, graded towards the target's foot."""
+    g, w = np.polynomial.legendre.leggauss(npts)
+    d0 = 0.25 * max(min(abs(xl - xt), abs(xr - xt), abs(yd - yt), abs(yu - yt)), abs(z))
+
+    def nodes(lo, hi, p):
+        b = _graded(lo, hi, p, d0)
+        a = 0.5 * (b[1:] - b[:-1])
+        c = 0.5 * (b[1:] + b[:-1])
+        return (c[:, None] + a[:, None] * g).ravel(), (a[:, None] * w).ravel()
+
+    xs, wx = nodes(xl, xr, xt)
+    ys, wy = nodes(yd, yu, yt)
+    XB, YB = np.meshgrid(xs, ys)
+    W = wy[:, None] * wx[None, :]
+    u, v = XB - xt, YB - yt
+    r3 = (u * u + v * v + z * z) ** 1.5
+    ex, ey = XB - 0.5 * (xl + xr), YB - 0.5 * (yd + yu)
+    out = []
+    for d in (u, v, -z * np.ones_like(u)):  # displacement source - target
+        out += [np.sum(W * d / r3), np.sum(W * ex * d / r3), np.sum(W * ey * d / r3)]
+    return np.array(out)
+
+
+@pytest.mark.parametrize("case", [
+    # (target, z, source rectangle)
+    ((0.0, 0.0), 0.3, (-0.5, 0.5, -0.5, 0.5)),     # above the centre of its own cell
+    ((0.2, -0.1), 0.05, (-0.5, 0.5, -0.5, 0.5)),   # low above an off-centre point
+    ((0.0, 0.0), -0.2, (0.5, 1.5, -0.5, 0.5)),     # below, right neighbour
+    ((0.0, 0.0), 0.7, (0.5, 1.5, 0.5, 1.5)),       # diagonal neighbour
+    ((0.0, 0.0), 0.1, (0.0, 1.0, 2.0, 3.0)),       # foot on an edge line
+    ((0.3, 0.7), 2.5, (-7.0, -6.0, 11.0, 13.0)),   # far, high
+])
+def test_offplane_kernels_match_quadrature(case):
+    (xt, yt), z, (xl, xr, yd, yu) = case
+    k = oracle.cell_kernels_z(xt, yt, z, xl, xr, yd, yu)
+    q = quad_kernels_z(xt, yt, z, xl, xr, yd, yu)
+    scale = np.max(np.abs(q))
+    np.testing.assert_allclose(k, q, rtol=1e-9, atol=1e-11 * scale)
+
+
+def test_offplane_limits_and_parity_in_z():
+    rect = (0.5, 1.5, -0.25, 0.75)
+    k0 = oracle.cell_kernels(0.0, 0.0, *rect)
+    for z in (1e-6, -1e-6):
+        kz = oracle.cell_kernels_z(0.0, 0.0, z, *rect)
+        np.testing.assert_allclose(kz[:6], k0, rtol=1e-9, atol=1e-12)   # in-plane limit
+        assert np.max(np.abs(kz[6:])) < 1e-5                              # no vertical pull
+    # directly above a cell the vertical kernel tends to -2 pi sgn(z) (the
+    # field of an infinite sheet)
+    for z in (1e-7, -1e-7):
+        kz = oracle.cell_kernels_z(0.1, -0.2, z, -0.5, 0.5, -0.5, 0.5)
+        assert abs(kz[6] + 2 * math.pi * math.copysign(1.0, z)) < 1e-5
+    # x and y families even in z, the z family odd
+    a = oracle.cell_kernels_z(0.3, -0.4, 0.6, *rect)
+    b = oracle.cell_kernels_z(0.3, -0.4, -0.6, *rect)
+    np.testing.assert_allclose(b[:6], a[:6], rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(b[6:], -a[6:], rtol=1e-14, atol=1e-16)
+    with pytest.raises(ValueError):
+        oracle.cell_kernels_z(0.0, 0.0, 0.0, *rect)
+
+
+def test_offplane_kuzmin_truncated():
+    """Kuzmin disk M = 1, a = 0.2 on [-1,1]^2, targets at height z above the
+    cell centres: against the analytic off-plane force minus the force of the
+    mass outside the square the error is second-order discretisation error;
+    against the untruncated force it stalls near 1%."""
+    for z in (0.05, 0.3):
+        errs = []
+        for n in (32, 64):
+            rng = np.random.default_rng(n)
+            X, Y = diskgen.grid_centres(n)
+            s, dx, dy = diskgen.kuzmin(X, Y, 1.0, 0.2)
+            h = 2.0 / n
+            rect = np.stack([X.ravel() - h / 2, X.ravel() + h / 2, Y.ravel() - h / 2,
+                             Y.ravel() + h / 2], 1)
+            sel = rng.choice(n * n, 100, replace=False)
+            tg = np.stack([X.ravel()[sel], Y.ravel()[sel]], 1)
+            f = oracle.direct_z(rect, s.ravel(), dx.ravel(), dy.ravel(), tg, z)
+            errs.append(an.rel_l2(f, an.kuzmin_truncated_force_z(tg[:, 0], tg[:, 1], z)))
+            assert 0.005 < an.rel_l2(f, an.kuzmin_force_z(tg[:, 0], tg[:, 1], z)) < 0.02
+        assert errs[1] < 3e-3
+        assert errs[0] / errs[1] > 3.3
+
+
+def test_offplane_additivity_linear_block():
+    """A density linear on a block of cells, with its exact slopes, gives at a
+    target above the plane the closed form of the whole block."""
+    h = 0.25
+    xs = -1.0 + h * np.arange(6)
+    ys = 0.5 + h * np.arange(4)
+    X, Y = np.meshgrid(xs + h / 2, ys + h / 2)
+    a, b, c = 0.7, -1.3, 2.1
+    s = a + b * X + c * Y
+    rect = np.stack([X.ravel() - h / 2, X.ravel() + h / 2, Y.ravel() - h / 2, Y.ravel() + h / 2], 1)
+    tg = np.array([[0.1, -0.3], [-0.6, 0.9], [2.0, 2.0]])
+    for z in (0.15, -0.8):
+        f = oracle.direct_z(rect, s.ravel(), np.full(s.size, b), np.full(s.size, c), tg, z)
+        xl, xr, yd, yu = xs[0], xs[-1] + h, ys[0], ys[-1] + h
+        sc = a + b * 0.5 * (xl + xr) + c * 0.5 * (yd + yu)
+        for i, (xt, yt) in enumerate(tg):
+            k = oracle.cell_kernels_z(xt, yt, z, xl, xr, yd, yu)
+            e = [sc * k[3 * m] + b * k[3 * m + 1] + c * k[3 * m + 2] for m in range(3)]
+            got = [f[0][i], f[1][i], f[2][i]]
+            np.testing.assert_allclose(got, e, rtol=1e-12, atol=1e-13 * max(map(abs, e)))
