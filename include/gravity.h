@@ -84,6 +84,9 @@ typedef struct {
     gravity_prec_t prec;
     gravity_slopes_t slopes;
     double G;                       /* gravitational constant */
+    double z;                       /* height of the target plane above the disk
+                                       (domain units); 0 = midplane (Fx, Fy),
+                                       otherwise (Fx, Fy, Fz) at that height */
 } gravity_desc_t;
 
 typedef struct {
@@ -94,15 +97,17 @@ typedef struct {
     size_t workspace_bytes;
     size_t resident_bytes; /* device memory held by the plan and its spectra */
     int32_t variants[3];   /* kernel variants in use (row forward, column, row inverse) */
+    int32_t ncomp;         /* force components: 2 (midplane) or 3 (off-plane) */
 } gravity_plan_info_t;
 
 /*
  * Create a plan: validates the descriptor and builds (or takes from the
  * resident cache) the kernel spectra for its FFT size and precision.  The
  * kernel tables are the exact integrals of Section 2 (K^{x,0}, K^{x,x},
- * K^{x,y} and the y family) at every source offset, built in double
- * precision on the device and transformed with a double precision FFT.
- * Sizes: 16 <= n_finest <= 4096, powers of two.
+ * K^{x,y} and the y family; with desc->z != 0 those at height z and the
+ * vertical family K^{z,0}, K^{z,x}, K^{z,y}) at every source offset, built
+ * in double precision on the device and transformed with a double precision
+ * FFT.  Sizes: 16 <= n_finest <= 4096, powers of two.
  * Kernel variants: unless GRAVITY_AUTOTUNE=0, the first plan of each size,
  * precision and layout kind times every variant of its three FFT kernels
  * and keeps the fastest (GRAVITY_TUNE_FILE persists the choices,
@@ -127,11 +132,25 @@ gravity_status_t gravity_plan_get_info(gravity_plan_t plan, gravity_plan_info_t 
  *   fx, fy          : composite-packed outputs (leaf forces, 0 elsewhere)
  *   workspace       : device buffer of gravity_plan_workspace_bytes bytes,
  *                     256-byte aligned, not shared with concurrent solves
- * Errors: EINVAL (NULL pointer, misaligned workspace), EDEVICE.
+ * Errors: EINVAL (NULL pointer, misaligned workspace, off-plane plan),
+ * EDEVICE.
  */
 gravity_status_t gravity_solve(gravity_plan_t plan, const void *sigma, const void *dsx,
                                const void *dsy, void *fx, void *fy, void *workspace,
                                void *stream);
+
+/*
+ * Off-plane solve (plans with desc->z != 0; Section 2 at general z): the
+ * force at height z above every leaf centre, as gravity_solve with a third
+ * composite-packed output fz (the vertical component; attraction towards
+ * the disk).  Errors: as gravity_solve; EINVAL for a midplane plan (use
+ * gravity_solve) or a NULL fz.  Off-plane plans are solved only through
+ * this call (gravity_solve, the batch, the profiling call and the server
+ * return EINVAL or EUNSUPPORTED for them).
+ */
+gravity_status_t gravity_solve_xyz(gravity_plan_t plan, const void *sigma, const void *dsx,
+                                   const void *dsy, void *fx, void *fy, void *fz,
+                                   void *workspace, void *stream);
 
 /* Workspace bytes for gravity_solve_batch over these n plans. */
 gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *plans,

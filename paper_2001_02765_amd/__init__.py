@@ -27,7 +27,7 @@ _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5
 
 # exported symbols of include/gravity.h
 SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
-           "gravity_solve", "gravity_batch_workspace_bytes", "gravity_solve_batch",
+           "gravity_solve", "gravity_solve_xyz", "gravity_batch_workspace_bytes", "gravity_solve_batch",
            "gravity_solve_profiled", "gravity_stage_name", "gravity_server_create",
            "gravity_server_submit", "gravity_server_poll", "gravity_server_wait",
            "gravity_server_drain", "gravity_server_get_stats", "gravity_server_reset_stats",
@@ -44,14 +44,15 @@ class DescT(ctypes.Structure):
     _fields_ = [("n0x", ctypes.c_int32), ("n0y", ctypes.c_int32), ("x0", ctypes.c_double),
                 ("y0", ctypes.c_double), ("h0", ctypes.c_double), ("nlevels", ctypes.c_int32),
                 ("npatches", ctypes.c_int32), ("patches", ctypes.POINTER(PatchT)),
-                ("prec", ctypes.c_int), ("slopes", ctypes.c_int), ("G", ctypes.c_double)]
+                ("prec", ctypes.c_int), ("slopes", ctypes.c_int), ("G", ctypes.c_double),
+                ("z", ctypes.c_double)]
 
 
 class InfoT(ctypes.Structure):
     _fields_ = [("n_finest", ctypes.c_int32), ("fft_size", ctypes.c_int32),
                 ("n_cells", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t),
-                ("variants", ctypes.c_int32 * 3)]
+                ("variants", ctypes.c_int32 * 3), ("ncomp", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -63,6 +64,8 @@ _lib.gravity_plan_get_info.argtypes = [_vp, ctypes.POINTER(InfoT)]
 _lib.gravity_plan_get_info.restype = ctypes.c_int
 _lib.gravity_solve.argtypes = [_vp] * 8
 _lib.gravity_solve.restype = ctypes.c_int
+_lib.gravity_solve_xyz.argtypes = [_vp] * 9
+_lib.gravity_solve_xyz.restype = ctypes.c_int
 _lib.gravity_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
                                                ctypes.POINTER(ctypes.c_size_t)]
 _lib.gravity_batch_workspace_bytes.restype = ctypes.c_int
@@ -140,11 +143,13 @@ class Plan:
 
     n0: base cells per side; nlevels: 1 for a uniform grid; patches: sequence
     of (level, i0, j0, nx, ny) with level >= 1 (base is level 0).  The domain
-    is [x0, x0 + n0 h0] x [y0, y0 + n0 h0] (default [-1, 1]^2).
+    is [x0, x0 + n0 h0] x [y0, y0 + n0 h0] (default [-1, 1]^2).  z: height of
+    the target plane above the disk (0: midplane, solved with ``solve``;
+    otherwise the three components at that height, with ``solve_xyz``).
     """
 
     def __init__(self, n0, prec=F32, slopes=True, G=1.0, x0=-1.0, y0=-1.0, h0=None,
-                 nlevels=1, patches=()):
+                 nlevels=1, patches=(), z=0.0):
         if h0 is None:
             h0 = 2.0 / n0
         pl = list(patches)
@@ -155,7 +160,7 @@ class Plan:
             self._patch_arr[k] = PatchT(*[int(v) for v in p])
         d = DescT(int(n0), int(n0), float(x0), float(y0), float(h0), int(nlevels), len(pl),
                   ctypes.cast(self._patch_arr, ctypes.POINTER(PatchT)), int(prec),
-                  SLOPES_GIVEN if slopes else SLOPES_NONE, float(G))
+                  SLOPES_GIVEN if slopes else SLOPES_NONE, float(G), float(z))
         h = _vp()
         _check(_lib.gravity_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -170,6 +175,8 @@ class Plan:
         self.workspace_bytes = info.workspace_bytes
         self.resident_bytes = info.resident_bytes
         self.variants = tuple(info.variants)
+        self.ncomp = info.ncomp
+        self.z = float(z)
 
     @property
     def handle(self):
@@ -218,6 +225,26 @@ class Plan:
                                   _ptr(workspace), _stream_handle(stream)))
         return fx, fy
 
+
+    def solve_xyz(self, sigma, dsx=None, dsy=None, fx=None, fy=None, fz=None, workspace=None,
+                  stream=None):
+        """Off-plane plans: queue a solve of (Fx, Fy, Fz) at height z above
+        every leaf centre; returns (fx, fy, fz), allocated if not given."""
+        import torch
+        dt = self.torch_dtype
+        for t in (sigma, dsx, dsy):
+            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("inputs must be contiguous %s CUDA tensors" % dt)
+            if t is not None and t.numel() != self.n_cells:
+                raise ValueError("inputs must hold %d composite-packed cells" % self.n_cells)
+        out = [o if o is not None else torch.empty(self.n_cells, dtype=dt, device=sigma.device)
+               for o in (fx, fy, fz)]
+        if workspace is None:
+            workspace = self.workspace()
+        _check(_lib.gravity_solve_xyz(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(out[0]),
+                                      _ptr(out[1]), _ptr(out[2]), _ptr(workspace),
+                                      _stream_handle(stream)))
+        return tuple(out)
 
     def profile(self, sigma, dsx, dsy, fx, fy, workspace, reps=20, stream=None):
         """Mean device milliseconds of one launch of each pipeline stage, each

@@ -167,18 +167,20 @@ std::shared_ptr<Twiddles> make_twiddles(int device, int M, int prec) {
     return t;
 }
 
-// six kernel spectra of one family at one size and precision: per kind the
-// odd x frequencies kx + 1/2, kx in [0, M/2), by the y frequencies ky in
-// [0, M/2] (a half plane; negative ky follow from the kind's parity in y)
+// the kernel spectra of one family at one size, precision and target height
+// (6 kinds in the midplane, 9 above it): per kind the odd x frequencies
+// kx + 1/2, kx in [0, M/2), by the y frequencies ky in [0, M/2] (a half
+// plane; negative ky follow from the kind's parity in y)
 struct KernelSet {
     int device, M, prec, family;
+    double zc;  // target height in finest cells
     DevBuf q;
     int64_t q_pitch, q_kstride;
 };
 
 std::mutex g_cache_mu;
 std::map<std::tuple<int, int, int>, std::weak_ptr<Twiddles>> g_tw_cache;
-std::map<std::tuple<int, int, int, int>, std::weak_ptr<KernelSet>> g_ks_cache;
+std::map<std::tuple<int, int, int, int, double>, std::weak_ptr<KernelSet>> g_ks_cache;
 
 std::shared_ptr<Twiddles> get_twiddles(int device, int M, int prec) {
     auto key = std::make_tuple(device, M, prec);
@@ -191,17 +193,19 @@ std::shared_ptr<Twiddles> get_twiddles(int device, int M, int prec) {
     return sp;
 }
 
-std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int family) {
+std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int family, double zc) {
     auto ks = std::make_shared<KernelSet>();
     ks->device = device;
     ks->M = M;
     ks->prec = prec;
     ks->family = family;
+    ks->zc = zc;
+    const int nkinds = zc != 0.0 ? 9 : 6;
     const int H = M / 2;
     ks->q_pitch = ((H + 1) + 63) / 64 * 64;
     ks->q_kstride = ks->q_pitch * H;
     const size_t esz = prec ? sizeof(double) : sizeof(float);
-    ks->q.alloc(6 * esz * ks->q_kstride, "kernel spectra");
+    ks->q.alloc(nkinds * esz * ks->q_kstride, "kernel spectra");
     // transient double-precision buffers
     DevBuf table(sizeof(double) * (size_t)M * M, "kernel table");
     DevBuf rows(sizeof(double) * 2 * (size_t)H * M, "kernel table row spectra");
@@ -210,9 +214,10 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
     ta.out = (double *)table.p;
     ta.M = M;
     ta.family = family;
+    ta.zc = zc;
     gauss_legendre(10, ta.glx, ta.glw);
     hipStream_t s = nullptr;
-    for (int kind = 0; kind < 6; ++kind) {
+    for (int kind = 0; kind < nkinds; ++kind) {
         ta.kind = kind;
         hip_check(launch_ktable(ta, s), "kernel table build");
         Pack<RowFwdArgs<double>> rp{};
@@ -225,7 +230,7 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
         ra.out_fstride = 0;
         hip_check(launch_row_fwd<double>(rp, 1, M, 0, false, M, 1, (const C<double> *)tw64->tw.p, s),
                   "kernel table row transform");
-        const int imag = (kind == 0 || kind == 3) ? 1 : 0;
+        const int imag = imag_kind(kind) ? 1 : 0;
         if (prec) {
             hip_check(launch_col_extract<double>((const C<double> *)rows.p, M,
                                                  (double *)ks->q.p + kind * ks->q_kstride, ks->q_pitch,
@@ -244,13 +249,13 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
     return ks;
 }
 
-std::shared_ptr<KernelSet> get_kernel_set(int device, int M, int prec, int family) {
-    auto key = std::make_tuple(device, M, prec, family);
+std::shared_ptr<KernelSet> get_kernel_set(int device, int M, int prec, int family, double zc) {
+    auto key = std::make_tuple(device, M, prec, family, zc);
     auto it = g_ks_cache.find(key);
     if (it != g_ks_cache.end()) {
         if (auto sp = it->second.lock()) return sp;
     }
-    auto sp = build_kernel_set(device, M, prec, family);
+    auto sp = build_kernel_set(device, M, prec, family, zc);
     g_ks_cache[key] = sp;
     return sp;
 }
@@ -273,6 +278,8 @@ struct gravity_plan_s {
     int M = 0;
     bool amr = false;
     int nfields = 3;
+    double z = 0.0;  // target height (domain units); 0: midplane
+    int ncomp = 2;   // force components: 2 in the midplane, 3 above it
     int64_t ncells = 0, nleaves = 0;
     std::shared_ptr<Twiddles> tw;
     std::shared_ptr<KernelSet> centre, corner;
@@ -404,12 +411,14 @@ struct Item {
     const void *s, *dx, *dy;
     void *fx, *fy;
     char *ws;
+    void *fz = nullptr;  // off-plane plans only
 };
 
 // Solves that can share every launch: same precision, size, fields, layout
 // kind and kernel variants.
 bool same_group(const gravity_plan_s &a, const gravity_plan_s &b) {
     return a.prec == b.prec && a.M == b.M && a.nfields == b.nfields && a.amr == b.amr &&
+           a.ncomp == b.ncomp &&
            a.var_rf == b.var_rf && a.var_col == b.var_col && a.var_ri == b.var_ri &&
            a.device == b.device;
 }
@@ -424,6 +433,7 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
     const int nf = p0.nf, M = p0.M, H = M / 2;
     const int NF = p0.nfields;
     const int nfam = p0.amr ? 2 : 1;
+    const int NC = p0.ncomp;
     const C<T> *tw = (const C<T> *)p0.tw->tw.p;
     const C<T> *ph = (const C<T> *)p0.tw->ph.p;
     const int64_t colsz = (int64_t)H * nf;  // M/2 spectral columns of nf rows
@@ -496,7 +506,7 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
     }
     mark();
     for (int r = 0; r < srep; ++r)
-        hip_check(launch_col<T>(cp, n, M, p0.var_col, NF, nfam, tw, ph, s), "column transform");
+        hip_check(launch_col<T>(cp, n, M, p0.var_col, NF, nfam, NC, tw, ph, s), "column transform");
 
     Pack<RowInvArgs<T>> ip{};
     for (int i = 0; i < n; ++i) {
@@ -510,14 +520,15 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
         if (!p.amr) {
             ia.out[0] = (T *)it[i].fx;
             ia.out[1] = (T *)it[i].fy;
+            ia.out[2] = (T *)it[i].fz;  // used when NC == 3
         } else {
             T *O = (T *)(it[i].ws + p.off_o);
-            for (int g = 0; g < 4; ++g) ia.out[g] = O + g * n2;
+            for (int g = 0; g < NC * nfam; ++g) ia.out[g] = O + g * n2;
         }
     }
     mark();
     for (int r = 0; r < srep; ++r)
-        hip_check(launch_row_inv<T>(ip, n, M, p0.var_ri, nf, 2 * nfam, tw, s), "inverse row transform");
+        hip_check(launch_row_inv<T>(ip, n, M, p0.var_ri, nf, NC * nfam, tw, s), "inverse row transform");
 
     if (p0.amr) {
         Pack<GatherArgs<T>> gp{};
@@ -526,10 +537,12 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
             const gravity_plan_s &p = *it[i].p;
             GatherArgs<T> &ga = gp.a[i];
             ga.gmap = (const int32_t *)p.gmap.p;
-            for (int g = 0; g < 4; ++g) ga.o[g] = ip.a[i].out[g];
+            for (int g = 0; g < NC * nfam; ++g) ga.o[g] = ip.a[i].out[g];
             ga.fx = (T *)it[i].fx;
             ga.fy = (T *)it[i].fy;
+            ga.fz = (T *)it[i].fz;
             ga.n = p.ncells;
+            ga.ncomp = NC;
             maxc = std::max<int64_t>(maxc, p.ncells);
         }
         mark();
@@ -548,8 +561,9 @@ void run_items(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr) {
 // single solve entry used by the autotuner and the profiling call
 template <typename T>
 void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const void *dsy, void *fx,
-             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr, int srep = 1) {
-    Item it{&p, sigma, dsx, dsy, fx, fy, ws};
+             void *fy, char *ws, hipStream_t s, hipEvent_t *ev = nullptr, int srep = 1,
+             void *fz = nullptr) {
+    Item it{&p, sigma, dsx, dsy, fx, fy, ws, fz};
     run_group<T>(&it, 1, s, ev, srep);
 }
 
@@ -562,7 +576,8 @@ void solve_t(const gravity_plan_s &p, const void *sigma, const void *dsx, const 
 struct Variants {
     int rf, col, ri;
 };
-std::map<std::tuple<std::string, int, int, int, int>, Variants> g_tuned;
+// key: device, M, precision, fields, families, components
+std::map<std::tuple<std::string, int, int, int, int, int>, Variants> g_tuned;
 bool g_tune_file_loaded = false;
 
 std::string device_key(int device) {
@@ -582,23 +597,24 @@ void load_tune_file() {
     FILE *f = std::fopen(path, "r");
     if (!f) return;
     char dev[256];
-    int M, prec, nf, nfam, rf, col, ri;
-    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d", dev, &M, &prec, &nf, &nfam, &rf, &col, &ri) == 8)
-        g_tuned[std::make_tuple(std::string(dev), M, prec, nf, nfam)] = Variants{rf, col, ri};
+    int M, prec, nf, nfam, nc, rf, col, ri;
+    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", dev, &M, &prec, &nf, &nfam, &nc, &rf, &col,
+                       &ri) == 9)
+        g_tuned[std::make_tuple(std::string(dev), M, prec, nf, nfam, nc)] = Variants{rf, col, ri};
     std::fclose(f);
 }
 
-void save_tune_entry(const std::string &dev, int M, int prec, int nf, int nfam, const Variants &v) {
+void save_tune_entry(const std::string &dev, int M, int prec, int nf, int nfam, int nc, const Variants &v) {
     const char *path = std::getenv("GRAVITY_TUNE_FILE");
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", dev.c_str(), M, prec, nf, nfam, v.rf, v.col, v.ri);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", dev.c_str(), M, prec, nf, nfam, nc, v.rf, v.col, v.ri);
     std::fclose(f);
 }
 
 bool col_ok(const gravity_plan_s &p, int v) {
-    return col_variant_valid(p.prec, p.M, v, p.nfields, p.amr ? 2 : 1);
+    return col_variant_valid(p.prec, p.M, v, p.nfields, p.amr ? 2 : 1, p.ncomp);
 }
 
 Variants default_variants(const gravity_plan_s &p) {
@@ -615,7 +631,7 @@ template <typename T> Variants autotune(gravity_plan_s &p) {
     const int s_rf = p.amr ? 1 : 0, s_col = p.amr ? 2 : 1, s_ri = p.amr ? 3 : 2;
     DevBuf ws(p.ws_bytes, "autotune workspace");
     DevBuf in(3 * sizeof(T) * (size_t)p.ncells, "autotune inputs");
-    DevBuf out(2 * sizeof(T) * (size_t)p.ncells, "autotune outputs");
+    DevBuf out(3 * sizeof(T) * (size_t)p.ncells, "autotune outputs");
     hip_check(hipMemset(in.p, 0, in.bytes), "autotune memset");
     const T *sg = (const T *)in.p;
     std::vector<hipEvent_t> ev(ns + 1, nullptr);
@@ -639,7 +655,7 @@ template <typename T> Variants autotune(gravity_plan_s &p) {
         double acc[8] = {0};
         for (int r = 0; r < 2; ++r) {  // warm-up, then every stage reps times back to back
             solve_t<T>(p, sg, sg + p.ncells, sg + 2 * p.ncells, out.p, (T *)out.p + p.ncells,
-                       (char *)ws.p, nullptr, ev.data(), r == 0 ? 1 : reps);
+                       (char *)ws.p, nullptr, ev.data(), r == 0 ? 1 : reps, (T *)out.p + 2 * p.ncells);
             hip_check(hipEventSynchronize(ev[ns]), "hipEventSynchronize");
             if (r == 0) continue;
             for (int k = 0; k < ns; ++k) {
@@ -672,7 +688,7 @@ void choose_variants(gravity_plan_s &p) {
     if (!(at && std::string(at) == "0")) {
         load_tune_file();
         const std::string dev = device_key(p.device);
-        auto key = std::make_tuple(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1);
+        auto key = std::make_tuple(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1, p.ncomp);
         auto it = g_tuned.find(key);
         // an entry of a tune file written by another build may name a
         // variant this build does not have: tune again then
@@ -682,7 +698,7 @@ void choose_variants(gravity_plan_s &p) {
         } else {
             v = p.prec ? autotune<double>(p) : autotune<float>(p);
             g_tuned[key] = v;
-            save_tune_entry(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1, v);
+            save_tune_entry(dev, p.M, p.prec, p.nfields, p.amr ? 2 : 1, p.ncomp, v);
         }
     }
     p.var_rf = v.rf;
@@ -701,7 +717,8 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         if (d->n0x != d->n0y) fail(GRAVITY_EUNSUPPORTED, "only square base grids are supported");
         if (!is_pow2(d->n0x)) fail(GRAVITY_EUNSUPPORTED, "base size must be a power of two");
         if (d->nlevels < 1 || d->nlevels > 8) fail(GRAVITY_EINVAL, "nlevels must be 1..8");
-        if (!(d->h0 > 0) || !std::isfinite(d->h0) || !std::isfinite(d->x0) || !std::isfinite(d->y0))
+        if (!(d->h0 > 0) || !std::isfinite(d->h0) || !std::isfinite(d->x0) || !std::isfinite(d->y0) ||
+            !std::isfinite(d->z))
             fail(GRAVITY_EINVAL, "bad geometry");
         if (d->prec != GRAVITY_F32 && d->prec != GRAVITY_F64) fail(GRAVITY_EINVAL, "bad precision");
         if (d->slopes != GRAVITY_SLOPES_NONE && d->slopes != GRAVITY_SLOPES_GIVEN)
@@ -715,6 +732,8 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         p->prec = d->prec;
         p->slopes = d->slopes;
         p->G = d->G;
+        p->z = d->z;
+        p->ncomp = d->z != 0.0 ? 3 : 2;
         p->n0 = d->n0x;
         p->nlevels = d->nlevels;
         p->x0 = d->x0;
@@ -735,8 +754,10 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             p->tw = get_twiddles(p->device, p->M, p->prec);
-            p->centre = get_kernel_set(p->device, p->M, p->prec, 0);
-            if (p->amr) p->corner = get_kernel_set(p->device, p->M, p->prec, 1);
+            // target height in finest cells (the kernel tables are in cell units)
+            const double zc = p->z / (p->h0 / (double)(1 << (p->nlevels - 1)));
+            p->centre = get_kernel_set(p->device, p->M, p->prec, 0, zc);
+            if (p->amr) p->corner = get_kernel_set(p->device, p->M, p->prec, 1, zc);
         }
         if (p->amr) {
             p->owner.alloc(owner.size() * sizeof(int32_t), "AMR owner map");
@@ -757,10 +778,10 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         p->off_a = off;
         off += align256(colsz * p->nfields);
         p->off_b = off;
-        off += align256(colsz * (p->amr ? 4 : 2));
+        off += align256(colsz * p->ncomp * (p->amr ? 2 : 1));
         if (p->amr) {
             p->off_o = off;
-            off += align256(esz * 4 * (size_t)(n * n));
+            off += align256(esz * 2 * p->ncomp * (size_t)(n * n));
         }
         p->ws_bytes = off;
         {
@@ -791,6 +812,7 @@ gravity_status_t gravity_plan_get_info(gravity_plan_t p, gravity_plan_info_t *in
         if (p->corner) r += p->corner->q.bytes;
         if (p->tw) r += p->tw->tw.bytes + p->tw->ph.bytes;
         info->resident_bytes = r;
+        info->ncomp = p->ncomp;
         info->variants[0] = p->var_rf;
         info->variants[1] = p->var_col;
         info->variants[2] = p->var_ri;
@@ -817,7 +839,20 @@ gravity_status_t gravity_solve(gravity_plan_t p, const void *sigma, const void *
                                void *fx, void *fy, void *workspace, void *stream) {
     return guarded([&] {
         check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
+        if (p->ncomp == 3) fail(GRAVITY_EINVAL, "off-plane plan: use gravity_solve_xyz");
         Item it{p, sigma, dsx, dsy, fx, fy, (char *)workspace};
+        run_items(&it, 1, (hipStream_t)stream);
+    });
+}
+
+gravity_status_t gravity_solve_xyz(gravity_plan_t p, const void *sigma, const void *dsx, const void *dsy,
+                                   void *fx, void *fy, void *fz, void *workspace, void *stream) {
+    return guarded([&] {
+        check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
+        if (p->ncomp != 3) fail(GRAVITY_EINVAL, "midplane plan: use gravity_solve");
+        if (!fz) fail(GRAVITY_EINVAL, "NULL array argument");
+        if (((uintptr_t)fz) & ((p->prec ? 16 : 8) - 1)) fail(GRAVITY_EINVAL, "arrays must be aligned to two elements");
+        Item it{p, sigma, dsx, dsy, fx, fy, (char *)workspace, fz};
         run_items(&it, 1, (hipStream_t)stream);
     });
 }
@@ -847,6 +882,8 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, con
             const void *dy = dsy ? dsy[i] : nullptr;
             char *ws = workspace ? (char *)workspace + off : nullptr;
             check_solve_args(plans[i], sigma[i], dx, dy, fx[i], fy[i], ws);
+            if (plans[i]->ncomp == 3)
+                fail(GRAVITY_EUNSUPPORTED, "off-plane plans are solved with gravity_solve_xyz");
             items.push_back(Item{plans[i], sigma[i], dx, dy, fx[i], fy[i], ws});
             off += align256(plans[i]->ws_bytes);
         }
@@ -876,6 +913,7 @@ gravity_status_t gravity_solve_profiled(gravity_plan_t p, const void *sigma, con
     gravity_status_t st = guarded([&] {
         check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
         if (reps < 1 || !stage_ms || !nstages) fail(GRAVITY_EINVAL, "bad profiling arguments");
+        if (p->ncomp == 3) fail(GRAVITY_EUNSUPPORTED, "off-plane plans are solved with gravity_solve_xyz");
         const int ns = n_stages(*p);
         ev.resize(ns + 1);
         for (auto &e : ev) {
@@ -1162,6 +1200,7 @@ gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t p, c
         if (!srv || !ticket) fail(GRAVITY_EINVAL, "NULL argument");
         alignas(256) static char aligned_dummy;
         check_solve_args(p, sigma, dsx, dsy, fx, fy, &aligned_dummy);
+        if (p->ncomp == 3) fail(GRAVITY_EUNSUPPORTED, "off-plane plans are solved with gravity_solve_xyz");
         if (p->device != srv->device) fail(GRAVITY_EINVAL, "plan and server are on different devices");
         const size_t ws = align256(p->ws_bytes);
         if (ws > srv->arena->size()) fail(GRAVITY_ENOMEM, "request workspace exceeds the server budget");

@@ -40,7 +40,7 @@ template <typename T> struct ColArgs {
 template <typename T> struct RowInvArgs {
     const C<T> *in;  // B
     int64_t in_pitch, in_gstride;
-    T *out[4];
+    T *out[6];       // one real plane per output (component x family)
     int64_t out_pitch;
     T scale;
 };
@@ -56,9 +56,10 @@ template <typename T> struct InjectArgs {
 
 template <typename T> struct GatherArgs {
     const int32_t *gmap;  // per composite cell: -1, or lattice index | family << 30
-    const T *o[4];        // centre Fx, Fy, corner Fx, Fy on the finest lattice
-    T *fx, *fy;
+    const T *o[6];        // finest-lattice outputs: component c of family f at o[ncomp f + c]
+    T *fx, *fy, *fz;      // fz only when ncomp == 3
     int64_t n;
+    int ncomp;
 };
 
 // Up to kPack independent solves of one size share a launch: the kernels
@@ -68,11 +69,24 @@ template <typename A> struct Pack {
     A a[kPack];
 };
 
+// Kernel kinds: 3 c + f is force component c (x, y, z) times input field f
+// (sigma, dsx, dsy): x0, xx, xy, y0, yx, yy, z0, zx, zy.
+// Parity in y: x0 even, xx even, xy odd, y0 odd, yx odd, yy even, z0 even,
+// zx even, zy odd.
+__host__ __device__ constexpr int parity_y(int kind) {
+    return (kind == 2 || kind == 3 || kind == 4 || kind == 8) ? -1 : 1;
+}
+// kinds whose spectrum is purely imaginary (odd in exactly one of x, y)
+__host__ __device__ constexpr bool imag_kind(int kind) {
+    return kind == 0 || kind == 3 || kind == 7 || kind == 8;
+}
+
 struct TableArgs {
-    double *out;  // M x M circulant table, row-major [my][mx]
+    double *out;  // M x M table, row-major [my][mx]
     int M;
     int family;   // 0: cell-centre targets, 1: lattice-corner targets
-    int kind;     // 0..5: x0, xx, xy, y0, yx, yy
+    int kind;     // 0..8: x0, xx, xy, y0, yx, yy, z0, zx, zy (z kinds need zc != 0)
+    double zc;    // height of the target plane above the disk, in cells (0: midplane)
     double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]
 };
 
@@ -83,7 +97,7 @@ struct TableArgs {
 // Validity depends on size, precision and fields.
 constexpr int kNumVariants = 12;
 bool row_variant_valid(int prec, int M, int var);
-bool col_variant_valid(int prec, int M, int var, int nfields, int nfam);
+bool col_variant_valid(int prec, int M, int var, int nfields, int nfam, int ncomp);
 
 // Launchers: n (1..kPack) items of the same size and kind in one launch.
 template <typename T>
@@ -91,7 +105,7 @@ hipError_t launch_row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int M, int var, b
                           int nrows, int nfields, const C<T> *tw, hipStream_t s);
 template <typename T>
 hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfields, int nfam,
-                      const C<T> *tw, const C<T> *ph, hipStream_t s);
+                      int ncomp, const C<T> *tw, const C<T> *ph, hipStream_t s);
 template <typename T>
 hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,
                           const C<T> *tw, hipStream_t s);

@@ -55,6 +55,48 @@ __device__ double closed_kernel(int kind, double uc, double vc, bool t0zero) {
     }
 }
 
+// Off-plane targets (height zc != 0 above the disk, in cells): the nine
+// kernels from the defining integrals with R = sqrt(u^2 + v^2 + zc^2),
+// a = |zc|:  K^{x,0} = -DD[ln(v + R)], I_uu = DD[v ln(u + R) - a atan(uv/(aR))],
+// I_uv = -DD[R], J = DD[atan(uv/(aR))]/a, K^{z,0} = -zc J, and
+// K^{.,x} = (x_t - x_c) K^{.,0} + ..., K^{z,x} = (x_t - x_c) K^{z,0} - zc K^{x,0}
+// (y family by symmetry).  ln(b + R) for b < 0 uses ln((R^2 - b^2)/(R - b)).
+__device__ double lnz(double b, double c, double a2) {
+    const double R = sqrt(b * b + c * c + a2);
+    return b >= 0.0 ? log(b + R) : log((c * c + a2) / (R - b));
+}
+__device__ double closed_kernel_z(int kind, double uc, double vc, double zc) {
+    const double us[2] = {uc - 0.5, uc + 0.5}, vs[2] = {vc - 0.5, vc + 0.5};
+    const double a = fabs(zc), a2 = a * a;
+    const double dxc = -uc, dyc = -vc;  // x_t - x_c, y_t - y_c
+    double kx0 = 0, ky0 = 0, iuu = 0, ivv = 0, iuv = 0, jj = 0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const double sg = ((i + j) & 1) ? -1.0 : 1.0;
+            const double u = us[i], v = vs[j];
+            const double R = sqrt(u * u + v * v + a2);
+            const double at = atan(u * v / (a * R));
+            kx0 -= sg * lnz(v, u, a2);
+            ky0 -= sg * lnz(u, v, a2);
+            iuu += sg * (v * lnz(u, v, a2) - a * at);
+            ivv += sg * (u * lnz(v, u, a2) - a * at);
+            iuv -= sg * R;
+            jj += sg * at;
+        }
+    const double kz0 = -zc * jj / a;
+    switch (kind) {
+        case 0: return kx0;
+        case 1: return dxc * kx0 + iuu;
+        case 2: return dyc * kx0 + iuv;
+        case 3: return ky0;
+        case 4: return dxc * ky0 + iuv;
+        case 5: return dyc * ky0 + ivv;
+        case 6: return kz0;
+        case 7: return dxc * kz0 - zc * kx0;
+        default: return dyc * kz0 - zc * ky0;
+    }
+}
+
 // The same integral by a 10 x 10 Gauss-Legendre rule, used for cells at
 // least 3.5 cells from the target: there the integrand is analytic in a
 // Bernstein ellipse of parameter >= 15 about the cell, so the rule's error
@@ -69,7 +111,7 @@ __device__ double quad_kernel(int kind, double uc, double vc, const TableArgs &a
         for (int jj = 0; jj < 10; ++jj) {
             const double dv = 0.5 * a.glx[jj];
             const double v = vc + dv;
-            const double r2 = u * u + v * v;
+            const double r2 = u * u + v * v + a.zc * a.zc;
             const double ir = 1.0 / sqrt(r2);
             const double ir3 = ir * ir * ir;
             double f;
@@ -79,7 +121,10 @@ __device__ double quad_kernel(int kind, double uc, double vc, const TableArgs &a
                 case 2: f = dv * u; break;
                 case 3: f = v; break;
                 case 4: f = du * v; break;
-                default: f = dv * v; break;
+                case 5: f = dv * v; break;
+                case 6: f = -a.zc; break;
+                case 7: f = -a.zc * du; break;
+                default: f = -a.zc * dv; break;
             }
             si += a.glw[jj] * f * ir3;
         }
@@ -119,6 +164,8 @@ __global__ void __launch_bounds__(256) k_ktable(TableArgs a) {
             const double distx = fmax(fabs(uc) - 0.5, 0.0), disty = fmax(fabs(vc) - 0.5, 0.0);
             if (fmax(distx, disty) >= 3.5) {
                 val = quad_kernel(a.kind, uc, vc, a);
+            } else if (a.zc != 0.0) {
+                val = closed_kernel_z(a.kind, uc, vc, a.zc);
             } else {
                 const bool t0zero = a.family == 1 && (dx == 0 || dx == -1) && (dy == 0 || dy == -1);
                 val = closed_kernel(a.kind, uc, vc, t0zero);
@@ -191,12 +238,14 @@ template <typename T> __global__ void __launch_bounds__(256) k_gather(Pack<Gathe
     if (m < 0) {
         a.fx[c] = 0;
         a.fy[c] = 0;
+        if (a.ncomp == 3) a.fz[c] = 0;
         return;
     }
     const int fam = (m >> 30) & 1;
     const int32_t pos = m & 0x3FFFFFFF;
-    a.fx[c] = a.o[2 * fam][pos];
-    a.fy[c] = a.o[2 * fam + 1][pos];
+    a.fx[c] = a.o[a.ncomp * fam][pos];
+    a.fy[c] = a.o[a.ncomp * fam + 1][pos];
+    if (a.ncomp == 3) a.fz[c] = a.o[3 * fam + 2][pos];
 }
 
 // ---------------------------------------------------------------------------
@@ -231,26 +280,28 @@ template <typename T, int M> static bool row_ok_t(int var) {
 template <int M> static bool row_ok(int prec, int var) {
     return prec ? row_ok_t<double, M>(var) : row_ok_t<float, M>(var);
 }
-template <typename T, int M, int NF, int NFAM> static bool col_ok(int var) {
+template <typename T, int M, int NF, int NFAM, int NC> static bool col_ok(int var) {
     switch (var) {
-        case 0: return col_var_ok<T, M, 0, NF, NFAM>();
-        case 1: return col_var_ok<T, M, 1, NF, NFAM>();
-        case 2: return col_var_ok<T, M, 2, NF, NFAM>();
-        case 3: return col_var_ok<T, M, 3, NF, NFAM>();
-        case 4: return col_var_ok<T, M, 4, NF, NFAM>();
-        case 6: return col_var_ok<T, M, 6, NF, NFAM>();
+        case 0: return col_var_ok<T, M, 0, NF, NFAM, NC>();
+        case 1: return col_var_ok<T, M, 1, NF, NFAM, NC>();
+        case 2: return col_var_ok<T, M, 2, NF, NFAM, NC>();
+        case 3: return col_var_ok<T, M, 3, NF, NFAM, NC>();
+        case 4: return col_var_ok<T, M, 4, NF, NFAM, NC>();
+        case 6: return col_var_ok<T, M, 6, NF, NFAM, NC>();
     }
     return false;
 }
-template <typename T, int M> static bool col_ok_k(int var, int nf, int nfam) {
-    if (nf == 3 && nfam == 1) return col_ok<T, M, 3, 1>(var);
-    if (nf == 3 && nfam == 2) return col_ok<T, M, 3, 2>(var);
-    if (nf == 1 && nfam == 1) return col_ok<T, M, 1, 1>(var);
-    if (nf == 1 && nfam == 2) return col_ok<T, M, 1, 2>(var);
+template <typename T, int M, int NC> static bool col_ok_k(int var, int nf, int nfam) {
+    if (nf == 3 && nfam == 1) return col_ok<T, M, 3, 1, NC>(var);
+    if (nf == 3 && nfam == 2) return col_ok<T, M, 3, 2, NC>(var);
+    if (nf == 1 && nfam == 1) return col_ok<T, M, 1, 1, NC>(var);
+    if (nf == 1 && nfam == 2) return col_ok<T, M, 1, 2, NC>(var);
     return false;
 }
-template <int M> static bool col_ok_p(int prec, int var, int nf, int nfam) {
-    return prec ? col_ok_k<double, M>(var, nf, nfam) : col_ok_k<float, M>(var, nf, nfam);
+template <int M> static bool col_ok_p(int prec, int var, int nf, int nfam, int nc) {
+    if (nc == 2) return prec ? col_ok_k<double, M, 2>(var, nf, nfam) : col_ok_k<float, M, 2>(var, nf, nfam);
+    if (nc == 3) return prec ? col_ok_k<double, M, 3>(var, nf, nfam) : col_ok_k<float, M, 3>(var, nf, nfam);
+    return false;
 }
 bool row_variant_valid(int prec, int M, int var) {
     switch (M) {
@@ -266,17 +317,17 @@ bool row_variant_valid(int prec, int M, int var) {
     }
     return false;
 }
-bool col_variant_valid(int prec, int M, int var, int nf, int nfam) {
+bool col_variant_valid(int prec, int M, int var, int nf, int nfam, int nc) {
     switch (M) {
-        case 32: return col_ok_p<32>(prec, var, nf, nfam);
-        case 64: return col_ok_p<64>(prec, var, nf, nfam);
-        case 128: return col_ok_p<128>(prec, var, nf, nfam);
-        case 256: return col_ok_p<256>(prec, var, nf, nfam);
-        case 512: return col_ok_p<512>(prec, var, nf, nfam);
-        case 1024: return col_ok_p<1024>(prec, var, nf, nfam);
-        case 2048: return col_ok_p<2048>(prec, var, nf, nfam);
-        case 4096: return col_ok_p<4096>(prec, var, nf, nfam);
-        case 8192: return col_ok_p<8192>(prec, var, nf, nfam);
+        case 32: return col_ok_p<32>(prec, var, nf, nfam, nc);
+        case 64: return col_ok_p<64>(prec, var, nf, nfam, nc);
+        case 128: return col_ok_p<128>(prec, var, nf, nfam, nc);
+        case 256: return col_ok_p<256>(prec, var, nf, nfam, nc);
+        case 512: return col_ok_p<512>(prec, var, nf, nfam, nc);
+        case 1024: return col_ok_p<1024>(prec, var, nf, nfam, nc);
+        case 2048: return col_ok_p<2048>(prec, var, nf, nfam, nc);
+        case 4096: return col_ok_p<4096>(prec, var, nf, nfam, nc);
+        case 8192: return col_ok_p<8192>(prec, var, nf, nfam, nc);
     }
     return false;
 }

@@ -3,7 +3,7 @@
 
 namespace grav {
 
-template hipError_t launch_col<float>(const Pack<ColArgs<float>> &, int, int, int, int, int,
+template hipError_t launch_col<float>(const Pack<ColArgs<float>> &, int, int, int, int, int, int,
                                     const C<float> *, const C<float> *, hipStream_t);
 
 }  // namespace grav

@@ -3,7 +3,7 @@
 
 namespace grav {
 
-template hipError_t launch_col<double>(const Pack<ColArgs<double>> &, int, int, int, int, int,
+template hipError_t launch_col<double>(const Pack<ColArgs<double>> &, int, int, int, int, int, int,
                                     const C<double> *, const C<double> *, hipStream_t);
 
 }  // namespace grav

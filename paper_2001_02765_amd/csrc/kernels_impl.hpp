@@ -73,7 +73,7 @@ template <typename T, int M, int V> constexpr bool row_var_ok() {
         return RowCfg<T, M, var_e(V), -1>::RPB < RowCfg<T, M, var_e(V), 0>::RPB;
     else return true;
 }
-template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok();
+template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col_var_ok();
 
 // ---------------------------------------------------------------------------
 // row forward, odd frequencies: X(k + 1/2) = sum_n x[n] exp(-2 pi i n (k+1/2)/M)
@@ -147,41 +147,37 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
 // exp(-i pi (kx + 1/2 + ky)/M) (targets half a cell from the source
 // lattice), applied once to the accumulated sums.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int parity_y(int kind) {
-    // x0 even, xx even, xy odd, y0 odd, yx odd, yy even (in y)
-    return (kind == 2 || kind == 3 || kind == 4) ? -1 : 1;
-}
 
-template <typename T, int M, int E, int NFAM>
+
+// NC force components (2 in the disk plane, 3 above it): output plane
+// NC fam + c accumulates component c of family fam; kind 3 c + f multiplies
+// field f.
+template <typename T, int M, int E, int NFAM, int NC>
 __device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, const ColArgs<T> &a,
                                         int kx, int t) {
     constexpr int NT = M / E, H = M / 2;
 #pragma unroll
     for (int fam = 0; fam < NFAM; ++fam) {
-        const T *qx = a.q[fam] + f * a.q_kstride + (int64_t)kx * a.q_pitch;
-        const T *qy = a.q[fam] + (3 + f) * a.q_kstride + (int64_t)kx * a.q_pitch;
-        const T sx = (T)parity_y(f), sy = (T)parity_y(3 + f);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int ky = t + NT * e;
-            const bool neg = ky > H;
-            const int kq = neg ? M - ky : ky;
-            T vx = qx[kq], vy = qy[kq];
-            if (neg) {
-                vx *= sx;
-                vy *= sy;
-            }
-            const C<T> X = x[e];
-            if (f == 0) {  // imaginary spectra: X * (i v)
-                acc[2 * fam][e].x -= X.y * vx;
-                acc[2 * fam][e].y += X.x * vx;
-                acc[2 * fam + 1][e].x -= X.y * vy;
-                acc[2 * fam + 1][e].y += X.x * vy;
-            } else {
-                acc[2 * fam][e].x += X.x * vx;
-                acc[2 * fam][e].y += X.y * vx;
-                acc[2 * fam + 1][e].x += X.x * vy;
-                acc[2 * fam + 1][e].y += X.y * vy;
+        for (int c = 0; c < NC; ++c) {
+            const int kind = 3 * c + f;
+            const T *q = a.q[fam] + kind * a.q_kstride + (int64_t)kx * a.q_pitch;
+            const T sg = (T)parity_y(kind);
+            C<T>(&o)[E] = acc[NC * fam + c];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int ky = t + NT * e;
+                const bool neg = ky > H;
+                T vq = q[neg ? M - ky : ky];
+                if (neg) vq *= sg;
+                const C<T> X = x[e];
+                if (imag_kind(kind)) {  // X * (i v)
+                    o[e].x -= X.y * vq;
+                    o[e].y += X.x * vq;
+                } else {
+                    o[e].x += X.x * vq;
+                    o[e].y += X.y * vq;
+                }
             }
         }
     }
@@ -193,35 +189,36 @@ __device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, co
 template <int M> using ColMap = std::conditional_t<(M <= 4096), LdsSwz, LdsSoA>;
 template <int M> constexpr int col_region() { return ColMap<M>::template region<M>(); }
 
-template <typename T, int M, int V, int NF, int NFAM> struct ColLds {
-    static constexpr int NB = var_all(V) ? cmax(NF, 2 * NFAM) : 1;
+template <typename T, int M, int V, int NF, int NFAM, int NC> struct ColLds {
+    static constexpr int NB = var_all(V) ? cmax(NF, NC * NFAM) : 1;
     static constexpr int N = NB * col_region<M>();
 };
 // a column variant exists if its transform has at least 2 threads and its
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
-template <typename T, int M, int V, int NF, int NFAM> constexpr bool col_var_ok() {
+template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col_var_ok() {
     if constexpr (V >= 8 || (V >= 4 && (V == 5 || V == 7 || M < 512))) return false;
+    else if constexpr (NC == 3 && V > 1) return false;  // off-plane: variants 0 and 1
     else if constexpr (V >= 4) return M >= 2 * var_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
     else if constexpr (NF == 1 && V != 0) return false;
     else if constexpr (M <= 256 && V > 1) return false;
-    else return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM>::N * (int)sizeof(C<T>) <= 163840;
+    else return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM, NC>::N * (int)sizeof(C<T>) <= 163840;
 }
 
-template <typename T, int M, int V, int NF, int NFAM>
+template <typename T, int M, int V, int NF, int NFAM, int NC>
 __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                          const C<T> *__restrict__ ph) {
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
     const ColMap<M> map{col_region<M>()};
-    __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM>::N];
+    __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
     const int t = threadIdx.x;
     const int kx = blockIdx.x;
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
 
-    C<T> acc[2 * NFAM][E];
+    C<T> acc[NC * NFAM][E];
 #pragma unroll
-    for (int g = 0; g < 2 * NFAM; ++g)
+    for (int g = 0; g < NC * NFAM; ++g)
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[g][e] = mk<T>(0, 0);
 
@@ -235,7 +232,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
         }
         fft_multi<T, M, NT, -1, NF>(x, lds, map, twr, t);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) col_mac<T, M, E, NFAM>(acc, x[f], f, a, kx, t);
+        for (int f = 0; f < NF; ++f) col_mac<T, M, E, NFAM, NC>(acc, x[f], f, a, kx, t);
     } else {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -244,7 +241,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 #pragma unroll
             for (int e = 0; e < E; ++e) x[0][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
             fft_multi<T, M, NT, -1, 1>(x, lds, map, twr, t);
-            col_mac<T, M, E, NFAM>(acc, x[0], f, a, kx, t);
+            col_mac<T, M, E, NFAM, NC>(acc, x[0], f, a, kx, t);
         }
     }
     if constexpr (NFAM == 2) {
@@ -254,18 +251,18 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
             const int ky = t + NT * e;
             const C<T> py = ky <= H ? ph[ky] : cconj<T>(ph[M - ky]);
             const C<T> p = cmul<T>(px, py);
-            acc[2][e] = cmul<T>(acc[2][e], p);
-            acc[3][e] = cmul<T>(acc[3][e], p);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[NC + c][e] = cmul<T>(acc[NC + c][e], p);
         }
     }
     if constexpr (var_all(V)) {
-        fft_multi<T, M, NT, +1, 2 * NFAM>(acc, lds, map, twr, t);
+        fft_multi<T, M, NT, +1, NC * NFAM>(acc, lds, map, twr, t);
     } else {
 #pragma unroll
-        for (int g = 0; g < 2 * NFAM; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
+        for (int g = 0; g < NC * NFAM; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
     }
 #pragma unroll
-    for (int g = 0; g < 2 * NFAM; ++g) {
+    for (int g = 0; g < NC * NFAM; ++g) {
         C<T> *dst = a.out + g * a.out_gstride + (int64_t)kx * a.out_pitch;
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) dst[t + NT * e] = acc[g][e];
@@ -276,7 +273,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 // after the other, but each transform runs for both columns in lockstep, so
 // the twiddle registers serve two columns and M/4 blocks (512 blocks of 32 KB
 // LDS at M = 2048 FP32: two per CU) run in a single dispatch round.
-template <typename T, int M, int V, int NF, int NFAM>
+template <typename T, int M, int V, int NF, int NFAM, int NC>
 __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                           const C<T> *__restrict__ ph) {
     constexpr int E = var_e(V), NT = M / E, H = M / 2;
@@ -287,11 +284,11 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
 
-    C<T> acc[2][2 * NFAM][E];
+    C<T> acc[2][NC * NFAM][E];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int g = 0; g < 2 * NFAM; ++g)
+        for (int g = 0; g < NC * NFAM; ++g)
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[c][g][e] = mk<T>(0, 0);
 
@@ -305,8 +302,8 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
             for (int e = 0; e < E; ++e) x[c][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
         }
         fft_multi<T, M, NT, -1, 2>(x, lds, map, twr, t);
-        col_mac<T, M, E, NFAM>(acc[0], x[0], f, a, kx0, t);
-        col_mac<T, M, E, NFAM>(acc[1], x[1], f, a, kx0 + 1, t);
+        col_mac<T, M, E, NFAM, NC>(acc[0], x[0], f, a, kx0, t);
+        col_mac<T, M, E, NFAM, NC>(acc[1], x[1], f, a, kx0 + 1, t);
     }
     if constexpr (NFAM == 2) {
 #pragma unroll
@@ -317,13 +314,13 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
                 const int ky = t + NT * e;
                 const C<T> py = ky <= H ? ph[ky] : cconj<T>(ph[M - ky]);
                 const C<T> p = cmul<T>(px, py);
-                acc[c][2][e] = cmul<T>(acc[c][2][e], p);
-                acc[c][3][e] = cmul<T>(acc[c][3][e], p);
+#pragma unroll
+                for (int g = NC; g < 2 * NC; ++g) acc[c][g][e] = cmul<T>(acc[c][g][e], p);
             }
         }
     }
 #pragma unroll
-    for (int g = 0; g < 2 * NFAM; ++g) {
+    for (int g = 0; g < NC * NFAM; ++g) {
         C<T> y[2][E];
 #pragma unroll
         for (int c = 0; c < 2; ++c)
@@ -339,13 +336,13 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
     }
 }
 
-template <typename T, int M, int V, int NF, int NFAM>
+template <typename T, int M, int V, int NF, int NFAM, int NC>
 __global__ void __launch_bounds__((M / var_e(V)))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
     if constexpr (var_dbl(V))
-        col2_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
+        col2_body<T, M, V, NF, NFAM, NC>(pk.a[blockIdx.z], tw, ph);
     else
-        col_body<T, M, V, NF, NFAM>(pk.a[blockIdx.z], tw, ph);
+        col_body<T, M, V, NF, NFAM, NC>(pk.a[blockIdx.z], tw, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,36 +454,43 @@ template <typename T, int M> struct Dispatch {
         }
         return hipErrorInvalidValue;
     }
-    template <int V, int NF, int NFAM>
+    template <int V, int NF, int NFAM, int NC>
     static hipError_t col_v(const Pack<ColArgs<T>> &a, int n, const C<T> *tw, const C<T> *ph,
                             hipStream_t s) {
-        if constexpr (!col_var_ok<T, M, V, NF, NFAM>()) {
+        if constexpr (!col_var_ok<T, M, V, NF, NFAM, NC>()) {
             return hipErrorInvalidValue;
         } else {
             const unsigned nblk = var_dbl(V) ? M / 4 : M / 2;
-            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM>), dim3(nblk, 1, n), dim3(M / var_e(V)), 0, s, a,
-                               tw, ph);
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, 1, n), dim3(M / var_e(V)), 0, s,
+                               a, tw, ph);
             return hipGetLastError();
         }
     }
-    template <int V>
-    static hipError_t col_nf(const Pack<ColArgs<T>> &a, int n, int nfields, int nfam, const C<T> *tw,
+    template <int V, int NC>
+    static hipError_t col_nc(const Pack<ColArgs<T>> &a, int n, int nfields, int nfam, const C<T> *tw,
                              const C<T> *ph, hipStream_t s) {
-        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1>(a, n, tw, ph, s);
-        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2>(a, n, tw, ph, s);
-        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1>(a, n, tw, ph, s);
-        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2>(a, n, tw, ph, s);
+        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1, NC>(a, n, tw, ph, s);
+        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2, NC>(a, n, tw, ph, s);
+        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1, NC>(a, n, tw, ph, s);
+        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2, NC>(a, n, tw, ph, s);
         return hipErrorInvalidValue;
     }
-    static hipError_t col(const Pack<ColArgs<T>> &a, int n, int var, int nfields, int nfam,
+    template <int V>
+    static hipError_t col_nf(const Pack<ColArgs<T>> &a, int n, int nfields, int nfam, int ncomp,
+                             const C<T> *tw, const C<T> *ph, hipStream_t s) {
+        if (ncomp == 2) return col_nc<V, 2>(a, n, nfields, nfam, tw, ph, s);
+        if (ncomp == 3) return col_nc<V, 3>(a, n, nfields, nfam, tw, ph, s);
+        return hipErrorInvalidValue;
+    }
+    static hipError_t col(const Pack<ColArgs<T>> &a, int n, int var, int nfields, int nfam, int ncomp,
                           const C<T> *tw, const C<T> *ph, hipStream_t s) {
         switch (var) {
-            case 0: return col_nf<0>(a, n, nfields, nfam, tw, ph, s);
-            case 1: return col_nf<1>(a, n, nfields, nfam, tw, ph, s);
-            case 2: return col_nf<2>(a, n, nfields, nfam, tw, ph, s);
-            case 3: return col_nf<3>(a, n, nfields, nfam, tw, ph, s);
-            case 4: return col_nf<4>(a, n, nfields, nfam, tw, ph, s);
-            case 6: return col_nf<6>(a, n, nfields, nfam, tw, ph, s);
+            case 0: return col_nf<0>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 1: return col_nf<1>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 2: return col_nf<2>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 3: return col_nf<3>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 4: return col_nf<4>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 6: return col_nf<6>(a, n, nfields, nfam, ncomp, tw, ph, s);
         }
         return hipErrorInvalidValue;
     }
@@ -531,9 +535,9 @@ hipError_t launch_row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int M, int var, b
 }
 template <typename T>
 hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfields, int nfam,
-                      const C<T> *tw, const C<T> *ph, hipStream_t s) {
+                      int ncomp, const C<T> *tw, const C<T> *ph, hipStream_t s) {
     if (n < 1 || n > kPack) return hipErrorInvalidValue;
-    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, n, var, nfields, nfam, tw, ph, s)))
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, n, var, nfields, nfam, ncomp, tw, ph, s)))
 }
 template <typename T>
 hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,

@@ -227,6 +227,102 @@ def test_amr_config3_sampled(gl, prec):
     assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
 
 
+# ---------------------------------------------------------------------------
+# off-plane targets (Section 2 at z != 0): (Fx, Fy, Fz) at height z
+# ---------------------------------------------------------------------------
+
+def _rects_uniform(n, h, x0=-1.0, y0=-1.0):
+    X, Y = diskgen.grid_centres(n, x0, y0, h)
+    rect = np.stack([X.ravel() - h / 2, X.ravel() + h / 2, Y.ravel() - h / 2, Y.ravel() + h / 2], 1)
+    return X, Y, rect
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("zcells", [0.5, -3.0])
+def test_offplane_uniform_full(gl, prec, zcells):
+    """Random linear density on a 64^2 grid, every cell centre at height z,
+    against the oracle's off-plane direct sum."""
+    n = 64
+    h = 2.0 / n
+    rng = np.random.default_rng(11)
+    s, dx, dy = rng.random((n, n)) + 0.1, rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    z = zcells * h
+    p = gl.Plan(n, _prec(gl, prec), h0=h, z=z)
+    assert p.ncomp == 3
+    f = p.solve_xyz(_dev(s, prec), _dev(dx, prec), _dev(dy, prec))
+    torch.cuda.synchronize()
+    X, Y, rect = _rects_uniform(n, h)
+    ref = oracle.direct_z(rect, s.ravel(), dx.ravel(), dy.ravel(), np.stack([X.ravel(), Y.ravel()], 1), z)
+    assert an.rel_l2([_host(c) for c in f], ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_offplane_noisy_spiral_256_sampled(gl, prec):
+    n = 256
+    s, dx, dy, h = diskgen.noisy_spiral(n, 4)
+    z = 0.02
+    p = gl.Plan(n, _prec(gl, prec), h0=h, z=z)
+    f = p.solve_xyz(_dev(s, prec), _dev(dx, prec), _dev(dy, prec))
+    torch.cuda.synchronize()
+    X, Y, rect = _rects_uniform(n, h)
+    sel = np.random.default_rng(5).choice(n * n, 200, replace=False)
+    ref = oracle.direct_z(rect, s.ravel(), dx.ravel(), dy.ravel(),
+                          np.stack([X.ravel()[sel], Y.ravel()[sel]], 1), z)
+    assert an.rel_l2([_host(c)[sel] for c in f], ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_offplane_amr_table10(gl, prec):
+    """The Appendix A layout at height z: every leaf against the leaf sum."""
+    lay = diskgen.table10_layout()
+    rng = np.random.default_rng(6)
+    m = lay.leaf_mask()
+    s, dx, dy = [np.where(m, a, 0) for a in (rng.random(lay.total()) + 0.2,
+                                               rng.standard_normal(lay.total()),
+                                               rng.standard_normal(lay.total()))]
+    z = 0.07
+    p = gl.Plan(lay.n0, _prec(gl, prec), x0=lay.x0, y0=lay.y0, h0=lay.h0, nlevels=lay.nlevels,
+                patches=lay.patches, z=z)
+    f = [_host(c) for c in p.solve_xyz(_dev(s, prec), _dev(dx, prec), _dev(dy, prec))]
+    torch.cuda.synchronize()
+    assert all(np.all(c[~m] == 0) for c in f)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    ref = oracle.direct_z(rect, s[idx], dx[idx], dy[idx], cent, z)
+    area = (rect[:, 1] - rect[:, 0]) * (rect[:, 3] - rect[:, 2])
+    assert an.rel_l2([c[idx] for c in f], ref, area) < TOL[prec]
+
+
+def test_offplane_small_height_tends_to_midplane(gl):
+    """(Fx, Fy) just above the disk approach the midplane solve."""
+    n = 128
+    s, dx, dy, h = diskgen.noisy_spiral(n, 7)
+    t = [_dev(a, "f64") for a in (s, dx, dy)]
+    mx, my = gl.Plan(n, gl.F64, h0=h).solve(*t)
+    fx, fy, fz = gl.Plan(n, gl.F64, h0=h, z=1e-6 * h).solve_xyz(*t)
+    torch.cuda.synchronize()
+    assert an.rel_l2((_host(fx), _host(fy)), (_host(mx), _host(my))) < 1e-5
+
+
+def test_offplane_entry_points(gl):
+    n = 32
+    p = gl.Plan(n, gl.F32, z=0.1)
+    q = gl.Plan(n, gl.F32)
+    a = torch.zeros(n * n, device="cuda")
+    with pytest.raises(gl.GravityError) as e:
+        p.solve(a, a, a)
+    assert e.value.status == gl.EINVAL
+    with pytest.raises(gl.GravityError) as e:
+        q.solve_xyz(a, a, a)
+    assert e.value.status == gl.EINVAL
+    ws = torch.empty(gl.batch_workspace_bytes([p]), dtype=torch.uint8, device="cuda")
+    with pytest.raises(gl.GravityError) as e:
+        gl.solve_batch([p], [a], [a], [a], [a.clone()], [a.clone()], ws)
+    assert e.value.status == gl.EUNSUPPORTED
+    with pytest.raises(gl.GravityError) as e:
+        gl.Plan(n, gl.F32, z=float("nan"))
+    assert e.value.status == gl.EINVAL
+
+
 def test_batch_bitwise_equals_single(gl):
     """Mixed sizes, precisions and layouts; more same-size solves than one
     launch carries (grouping splits them), results bit-identical to singles."""
