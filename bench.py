@@ -140,6 +140,23 @@ def amr_leg(gl, torch, reps):
     return out
 
 
+def offplane_leg(gl, torch, reps, fields, n):
+    """The headline disk with targets at height z = 0.05 above every cell
+    centre (25.6 cells at 1024^2): (Fx, Fy, Fz) per cell."""
+    s, dx, dy, h = fields
+    z = 0.05
+    out = {"workload": "uniform %dx%d cells, zero-padded %d^2 FFT, targets at height z = %g "
+                       "above the cell centres, (Fx, Fy, Fz)" % (n, n, 2 * n, z)}
+    for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
+        p = gl.Plan(n, prec, h0=h, z=z)
+        t = [torch.from_numpy(a.ravel()).to("cuda", dt) for a in (s, dx, dy)]
+        fo = [torch.empty(n * n, dtype=dt, device="cuda") for _ in range(3)]
+        ws = p.workspace()
+        ms = _timeit(torch, lambda: p.solve_xyz(*t, *fo, workspace=ws), reps)
+        out[name] = {"ms": ms, "forces_per_s": n * n / (ms * 1e-3), "variants": list(p.variants)}
+    return out
+
+
 def batch_leg(gl, torch, reps):
     """64 independent disks of mixed sizes in one gravity_solve_batch (FP32)
     against the same 64 solves issued one by one."""
@@ -324,7 +341,7 @@ def main():
 
     col_ms = r32["stages_ms"]["col"]
     achieved = col_bytes(n, 4) / (col_ms * 1e-3) / 1e9
-    kname = "grav::k_col<float, %d, %d, 3, 1>" % (2 * n, r32["variants"][1])
+    kname = "grav::k_col<float, %d, %d, 3, 1, 2>" % (2 * n, r32["variants"][1])
     roof = {"bound": "hbm", "kernel": kname + " (fused column transform, FP32)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, n),
@@ -348,11 +365,13 @@ def main():
                    "n": n, "fft": 2 * n, "slopes": True},
         "latency_ms": r32["latency_ms"],
         "stages_ms": r32["stages_ms"],
+        "variants": r32["variants"],
         "fp64": r64,
         "roofline": roof,
     }
     if not args.no_extra:
         out["amr"] = amr_leg(gl, torch, max(10, args.steps // 4))
+        out["offplane"] = offplane_leg(gl, torch, max(10, args.steps // 4), fields, n)
         out["batch"] = batch_leg(gl, torch, max(5, args.steps // 20))
         out["serve"] = serve_leg(gl, torch, nreq=max(100, 2 * args.steps))
     if not args.no_cpu_baseline:
