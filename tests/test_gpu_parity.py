@@ -303,6 +303,46 @@ def test_offplane_small_height_tends_to_midplane(gl):
     assert an.rel_l2((_host(fx), _host(fy)), (_host(mx), _host(my))) < 1e-5
 
 
+def test_amr_and_offplane_without_slopes(gl):
+    """Piecewise-constant leaves (one input field) on the AMR path, in the
+    plane and above it."""
+    lay = diskgen.table10_layout()
+    rng = np.random.default_rng(8)
+    m = lay.leaf_mask()
+    s = np.where(m, rng.random(lay.total()) + 0.2, 0)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    area = (rect[:, 1] - rect[:, 0]) * (rect[:, 3] - rect[:, 2])
+    kw = dict(x0=lay.x0, y0=lay.y0, h0=lay.h0, nlevels=lay.nlevels, patches=lay.patches, slopes=False)
+    fx, fy = gl.Plan(lay.n0, gl.F64, **kw).solve(_dev(s, "f64"))
+    torch.cuda.synchronize()
+    ox, oy = oracle.direct(rect, s[idx], None, None, cent)
+    assert an.rel_l2((_host(fx)[idx], _host(fy)[idx]), (ox, oy), area) < TOL["f64"]
+    f = gl.Plan(lay.n0, gl.F64, z=-0.04, **kw).solve_xyz(_dev(s, "f64"))
+    torch.cuda.synchronize()
+    ref = oracle.direct_z(rect, s[idx], None, None, cent, -0.04)
+    assert an.rel_l2([_host(c)[idx] for c in f], ref, area) < TOL["f64"]
+
+
+def test_injected_allocation_failure_recovers(gl, monkeypatch):
+    """With every device allocation failing, a plan that needs new kernel
+    spectra reports ENOMEM; once allocations succeed again the same plan
+    builds and solves correctly (no half-built spectra are cached)."""
+    n = 32  # no earlier test built spectra for this size at this height
+    monkeypatch.setenv("GRAVITY_FAIL_ALLOC_AFTER", "0")
+    with pytest.raises(gl.GravityError) as e:
+        gl.Plan(n, gl.F64, z=0.123)
+    assert e.value.status == gl.ENOMEM
+    monkeypatch.delenv("GRAVITY_FAIL_ALLOC_AFTER")
+    p = gl.Plan(n, gl.F64, z=0.123)
+    rng = np.random.default_rng(12)
+    s = rng.random((n, n))
+    f = p.solve_xyz(_dev(s, "f64"), _dev(np.zeros((n, n)), "f64"), _dev(np.zeros((n, n)), "f64"))
+    torch.cuda.synchronize()
+    X, Y, rect = _rects_uniform(n, 2.0 / n)
+    ref = oracle.direct_z(rect, s.ravel(), None, None, np.stack([X.ravel(), Y.ravel()], 1), 0.123)
+    assert an.rel_l2([_host(c) for c in f], ref) < TOL["f64"]
+
+
 def test_offplane_entry_points(gl):
     n = 32
     p = gl.Plan(n, gl.F32, z=0.1)
