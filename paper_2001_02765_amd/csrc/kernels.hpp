@@ -115,8 +115,9 @@ template <typename T>
 hipError_t launch_gather(const Pack<GatherArgs<T>> &a, int n, int64_t maxcells, hipStream_t s);
 
 hipError_t launch_ktable(const TableArgs &a, hipStream_t s);
-// forward FFT of the columns of a table's row spectra and extraction of one
-// real quadrant: Q[kx][ky] = part(e^{i pi corner (kx+ky)/M} S[ky][kx])
+// forward FFT of the columns of a table's row spectra (odd x frequencies)
+// and extraction of one real half plane, kx in [0, M/2), ky in [0, M/2]:
+// Q[kx][ky] = part(e^{i pi corner (kx + 1/2 + ky)/M} S[ky][kx])
 template <typename TQ>
 hipError_t launch_col_extract(const C<double> *in, int M, TQ *q, int64_t q_pitch, int imag,
                               int corner, const C<double> *tw, const C<double> *ph,

@@ -3,7 +3,7 @@
 //
 //  k_ktable      exact cell-integrated kernels at every source offset (FP64)
 //  k_col_extract forward column transform of a table's row spectra and
-//                storage of one real quadrant
+//                storage of one real half plane (ky in [0, M/2])
 //  k_inject      AMR: composite leaves -> finest lattice (linear density)
 //  k_gather      AMR: finest-lattice forces -> composite leaf outputs
 #include "kernels_impl.hpp"

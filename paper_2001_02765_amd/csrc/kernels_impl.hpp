@@ -1,8 +1,8 @@
 // Solve-path kernels (templates) and their launch dispatch.  Instantiated per
-// precision in kernels_f32.hip / kernels_f64.hip.
+// precision and kernel in kernels_{f32,f64}_{row,col}.hip.
 //
-//  k_row_fwd   real-to-complex row transforms of zero-padded fields,
-//              written transposed (column-major spectra)
+//  k_row_fwd   real-to-complex row transforms of zero-padded fields at the
+//              odd frequencies k + 1/2, written transposed (column-major)
 //  k_col       per spectral column: forward column transforms of the input
 //              fields, products with the kernel spectra, inverse column
 //              transforms of the force components
