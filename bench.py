@@ -236,7 +236,7 @@ def serve_leg(gl, torch, nreq, rho=0.8, budget=8 << 30):
             "batches": st["batches"]}
 
 
-def cpu_baseline(n, fields, budget_s=15.0):
+def cpu_baseline(n, fields, budget_s=25.0):
     """The oracle's direct leaf sum (exact kernels per source cell, FP64,
     compensated) on a seeded sample of target cells of the same workload,
     every source included.  Returns forces/s and the thread count."""

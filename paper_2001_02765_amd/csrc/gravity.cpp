@@ -287,7 +287,7 @@ struct gravity_plan_s {
     // kernel variants (row forward, column, row inverse), chosen at plan time
     int var_rf = 0, var_col = 0, var_ri = 0;
     // workspace layout (byte offsets)
-    size_t off_w = 0, off_a = 0, off_b = 0, off_o = 0, ws_bytes = 0;
+    size_t off_a = 0, off_b = 0, off_o = 0, ws_bytes = 0;
 };
 
 namespace {
@@ -401,9 +401,9 @@ template <typename F> gravity_status_t guarded(F &&fn) {
 }
 
 const char *const kStagesUniform[] = {"row_fwd", "col", "row_inv"};
-const char *const kStagesAmr[] = {"inject", "row_fwd", "col", "row_inv", "gather"};
+const char *const kStagesAmr[] = {"row_fwd", "col", "row_inv", "gather"};
 
-int n_stages(const gravity_plan_s &p) { return p.amr ? 5 : 3; }
+int n_stages(const gravity_plan_s &p) { return p.amr ? 4 : 3; }
 
 // One solve's arguments (device pointers) and workspace.
 struct Item {
@@ -448,16 +448,14 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
         const gravity_plan_s &p = *it[i].p;
         const T h = (T)(p.h0 / (double)(1 << (p.nlevels - 1)));
         RowFwdArgs<T> &ra = rf.a[i];
-        if (!p.amr) {
-            ra.in[0] = (const T *)it[i].s;
-            ra.in[1] = (const T *)it[i].dx;
-            ra.in[2] = (const T *)it[i].dy;
-        } else {
-            T *W = (T *)(it[i].ws + p.off_w);
-            ra.in[0] = W;
-            ra.in[1] = W + n2;
-            ra.in[2] = W + 2 * n2;
-        }
+        // uniform: the caller's fields; AMR: the leaf arrays, injected onto
+        // the finest lattice by the row kernel's load through the owner map
+        ra.in[0] = (const T *)it[i].s;
+        ra.in[1] = (const T *)it[i].dx;
+        ra.in[2] = (const T *)it[i].dy;
+        ra.owner = p.amr ? (const int32_t *)p.owner.p : nullptr;
+        ra.hf = h;
+        ra.slopes = NF == 3;
         ra.scale[0] = (T)1;
         ra.scale[1] = h;
         ra.scale[2] = h;
@@ -465,25 +463,6 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
         ra.out = (C<T> *)(it[i].ws + p.off_a);
         ra.out_pitch = nf;
         ra.out_fstride = colsz;
-    }
-    if (p0.amr) {
-        Pack<InjectArgs<T>> ip{};
-        for (int i = 0; i < n; ++i) {
-            const gravity_plan_s &p = *it[i].p;
-            InjectArgs<T> &ia = ip.a[i];
-            ia.s = (const T *)it[i].s;
-            ia.dx = (const T *)it[i].dx;
-            ia.dy = (const T *)it[i].dy;
-            ia.owner = (const int32_t *)p.owner.p;
-            ia.w0 = (T *)rf.a[i].in[0];
-            ia.w1 = (T *)rf.a[i].in[1];
-            ia.w2 = (T *)rf.a[i].in[2];
-            ia.nf = nf;
-            ia.hf = rf.a[i].scale[1];
-            ia.slopes = NF == 3;
-        }
-        mark();
-        for (int r = 0; r < srep; ++r) hip_check(launch_inject<T>(ip, n, nf, s), "inject");
     }
     mark();
     for (int r = 0; r < srep; ++r)
@@ -628,7 +607,7 @@ Variants default_variants(const gravity_plan_s &p) {
 template <typename T> Variants autotune(gravity_plan_s &p) {
     const int M = p.M;
     const int ns = n_stages(p);
-    const int s_rf = p.amr ? 1 : 0, s_col = p.amr ? 2 : 1, s_ri = p.amr ? 3 : 2;
+    const int s_rf = 0, s_col = 1, s_ri = 2;  // stage indices (AMR adds the gather last)
     DevBuf ws(p.ws_bytes, "autotune workspace");
     DevBuf in(3 * sizeof(T) * (size_t)p.ncells, "autotune inputs");
     DevBuf out(3 * sizeof(T) * (size_t)p.ncells, "autotune outputs");
@@ -771,10 +750,6 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         const int64_t n = p->nf, H = p->M / 2;
         const size_t colsz = 2 * esz * (size_t)(H * n);
         size_t off = 0;
-        if (p->amr) {
-            p->off_w = off;
-            off += align256(esz * p->nfields * (size_t)(n * n));
-        }
         p->off_a = off;
         off += align256(colsz * p->nfields);
         p->off_b = off;

@@ -20,12 +20,18 @@ constexpr int kMinM = 32;
 constexpr int kMaxM = 8192;
 
 template <typename T> struct RowFwdArgs {
-    const T *in[3];     // up to three real fields
+    const T *in[3];     // up to three real fields (AMR: composite-packed leaf arrays)
     T scale[3];         // per-field multiplier applied on load
-    int64_t in_pitch;   // elements between input rows
+    int64_t in_pitch;   // elements between input rows (AMR: finest lattice side)
     C<T> *out;          // A
     int64_t out_pitch;  // elements between kx columns of A (= rows)
     int64_t out_fstride;
+    // AMR: each finest cell's value is injected on load from the leaf that
+    // covers it (owner: leaf index | log2(leaf size in finest cells) << 28),
+    // the leaf's linear density taken at the cell centre; hf = finest cell size
+    const int32_t *owner;
+    T hf;
+    int slopes;
 };
 
 template <typename T> struct ColArgs {
@@ -43,15 +49,6 @@ template <typename T> struct RowInvArgs {
     T *out[6];       // one real plane per output (component x family)
     int64_t out_pitch;
     T scale;
-};
-
-template <typename T> struct InjectArgs {
-    const T *s, *dx, *dy;  // composite-packed leaf values
-    const int32_t *owner;  // per finest cell: leaf index | log2(block) << 28
-    T *w0, *w1, *w2;       // finest-lattice fields
-    int nf;
-    T hf;
-    int slopes;
 };
 
 template <typename T> struct GatherArgs {
@@ -109,8 +106,6 @@ hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfie
 template <typename T>
 hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,
                           const C<T> *tw, hipStream_t s);
-template <typename T>
-hipError_t launch_inject(const Pack<InjectArgs<T>> &a, int n, int nf, hipStream_t s);
 template <typename T>
 hipError_t launch_gather(const Pack<GatherArgs<T>> &a, int n, int64_t maxcells, hipStream_t s);
 

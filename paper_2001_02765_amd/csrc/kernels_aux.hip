@@ -1,10 +1,9 @@
-// Auxiliary kernels: kernel tables and their spectra (plan time), AMR
-// injection and gather.
+// Auxiliary kernels: kernel tables and their spectra (plan time) and the AMR
+// gather (the AMR injection is fused into the row transform's load).
 //
 //  k_ktable      exact cell-integrated kernels at every source offset (FP64)
 //  k_col_extract forward column transform of a table's row spectra and
 //                storage of one real half plane (ky in [0, M/2])
-//  k_inject      AMR: composite leaves -> finest lattice (linear density)
 //  k_gather      AMR: finest-lattice forces -> composite leaf outputs
 #include "kernels_impl.hpp"
 
@@ -201,35 +200,8 @@ __global__ void __launch_bounds__((ExtractCfg<M>::NT))
 }
 
 // ---------------------------------------------------------------------------
-// AMR injection and gather
+// AMR gather
 // ---------------------------------------------------------------------------
-template <typename T> __global__ void __launch_bounds__(256) k_inject(Pack<InjectArgs<T>> pk) {
-    const InjectArgs<T> &a = pk.a[blockIdx.z];
-    const int64_t n2 = (int64_t)a.nf * a.nf;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n2) return;
-    const int I = (int)(idx % a.nf), J = (int)(idx / a.nf);
-    const int32_t o = a.owner[idx];
-    const int32_t c = o & 0x0FFFFFFF;
-    const int kb = (o >> 28) & 0xF;
-    const int B = 1 << kb;
-    T s = a.s[c];
-    T dx = 0, dy = 0;
-    if (a.slopes) {
-        dx = a.dx[c];
-        dy = a.dy[c];
-        // offset of this finest cell's centre from the leaf centre
-        const T ox = (T)(2 * (I & (B - 1)) + 1 - B) * (T)0.5 * a.hf;
-        const T oy = (T)(2 * (J & (B - 1)) + 1 - B) * (T)0.5 * a.hf;
-        s = s + dx * ox + dy * oy;
-    }
-    a.w0[idx] = s;
-    if (a.slopes) {
-        a.w1[idx] = dx;
-        a.w2[idx] = dy;
-    }
-}
-
 template <typename T> __global__ void __launch_bounds__(256) k_gather(Pack<GatherArgs<T>> pk) {
     const GatherArgs<T> &a = pk.a[blockIdx.z];
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,13 +305,6 @@ bool col_variant_valid(int prec, int M, int var, int nf, int nfam, int nc) {
 }
 
 template <typename T>
-hipError_t launch_inject(const Pack<InjectArgs<T>> &a, int n, int nf, hipStream_t s) {
-    if (n < 1 || n > kPack) return hipErrorInvalidValue;
-    const int64_t n2 = (int64_t)nf * nf;
-    hipLaunchKernelGGL((k_inject<T>), dim3((unsigned)((n2 + 255) / 256), 1, n), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-template <typename T>
 hipError_t launch_gather(const Pack<GatherArgs<T>> &a, int n, int64_t maxcells, hipStream_t s) {
     if (n < 1 || n > kPack) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)((maxcells + 255) / 256), 1, n), dim3(256), 0, s,
@@ -360,8 +325,6 @@ hipError_t launch_col_extract(const C<double> *in, int M, TQ *q, int64_t q_pitch
     GRAV_SWITCH_M(M, return (col_extract_m<TQ, MM>(in, q, q_pitch, imag, corner, tw, ph, s)))
 }
 
-template hipError_t launch_inject<float>(const Pack<InjectArgs<float>> &, int, int, hipStream_t);
-template hipError_t launch_inject<double>(const Pack<InjectArgs<double>> &, int, int, hipStream_t);
 template hipError_t launch_gather<float>(const Pack<GatherArgs<float>> &, int, int64_t, hipStream_t);
 template hipError_t launch_gather<double>(const Pack<GatherArgs<double>> &, int, int64_t, hipStream_t);
 template hipError_t launch_col_extract<float>(const C<double> *, int, float *, int64_t, int, int,

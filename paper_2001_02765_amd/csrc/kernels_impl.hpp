@@ -83,7 +83,25 @@ template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col
 // independent odd-frequency bins (X(M-1-k+1/2) = conj X(k+1/2)), all
 // complex, so there is no separate real Nyquist bin.
 // ---------------------------------------------------------------------------
-template <typename T, int M, int V, bool PRUNED>
+// AMR inject, fused into the row load: the value of field f at finest cell
+// (x, j) from the leaf covering it (Section 2: each leaf's density is linear,
+// and the integral is additive over the finest cells it covers).
+template <typename T>
+__device__ __forceinline__ T inject_value(const RowFwdArgs<T> &a, int f, int64_t j, int x) {
+    const int32_t o = a.owner[j * a.in_pitch + x];
+    const int32_t c = o & 0x0FFFFFFF;
+    if (f != 0) return a.in[f][c];
+    T s = a.in[0][c];
+    if (a.slopes) {
+        const int B = 1 << ((o >> 28) & 0xF);
+        const T ox = (T)(2 * (x & (B - 1)) + 1 - B) * (T)0.5 * a.hf;
+        const T oy = (T)(2 * ((int)j & (B - 1)) + 1 - B) * (T)0.5 * a.hf;
+        s = s + a.in[1][c] * ox + a.in[2][c] * oy;
+    }
+    return s;
+}
+
+template <typename T, int M, int V, bool PRUNED, bool INJ>
 __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     k_row_fwd(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
     const RowFwdArgs<T> &a = pk.a[blockIdx.z];
@@ -102,7 +120,7 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     const int f0 = var_all(V) ? 0 : (int)blockIdx.y;
     const int f1 = var_all(V) ? nfields : f0 + 1;
     for (int f = f0; f < f1; ++f) {
-        const C<T> *row = reinterpret_cast<const C<T> *>(a.in[f] + j * a.in_pitch);
+        const C<T> *row = INJ ? nullptr : reinterpret_cast<const C<T> *>(a.in[f] + j * a.in_pitch);
         const T sc = a.scale[f];
         C<T> reg[1][E];
 #pragma unroll
@@ -111,7 +129,8 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
                 reg[0][e] = mk<T>(0, 0);
             } else {
                 const int m = tr + NTR * e;
-                const C<T> v = row[m];
+                const C<T> v = INJ ? mk<T>(inject_value<T>(a, f, j, 2 * m), inject_value<T>(a, f, j, 2 * m + 1))
+                                   : row[m];
                 reg[0][e] = cmul<T>(mk<T>(v.x * sc, v.y * sc), tw[m]);
             }
         }
@@ -429,10 +448,14 @@ template <typename T, int M> struct Dispatch {
             using CF = RowCfg<T, M, var_e(V), row_scale(V)>;
             if (nrows % CF::RPB) return hipErrorInvalidValue;
             dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields, n);
-            if (pruned)
-                hipLaunchKernelGGL((k_row_fwd<T, M, V, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+            if (pruned && a.a[0].owner)  // AMR: every item of a pack shares the layout kind
+                hipLaunchKernelGGL((k_row_fwd<T, M, V, true, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+            else if (pruned)
+                hipLaunchKernelGGL((k_row_fwd<T, M, V, true, false>), grid, dim3(CF::NTH), 0, s, a, nfields,
+                                   tw);
             else
-                hipLaunchKernelGGL((k_row_fwd<T, M, V, false>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
+                hipLaunchKernelGGL((k_row_fwd<T, M, V, false, false>), grid, dim3(CF::NTH), 0, s, a, nfields,
+                                   tw);
             return hipGetLastError();
         }
     }
