@@ -260,6 +260,8 @@ template <typename T, int M, int NF, int NFAM, int NC> static bool col_ok(int va
         case 3: return col_var_ok<T, M, 3, NF, NFAM, NC>();
         case 4: return col_var_ok<T, M, 4, NF, NFAM, NC>();
         case 6: return col_var_ok<T, M, 6, NF, NFAM, NC>();
+        case 8: return col_var_ok<T, M, 8, NF, NFAM, NC>();
+        case 9: return col_var_ok<T, M, 9, NF, NFAM, NC>();
     }
     return false;
 }

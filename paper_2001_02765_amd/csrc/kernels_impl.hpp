@@ -63,6 +63,9 @@ constexpr int var_e(int v) { return (v & 2) ? 16 : 8; }
 constexpr bool var_all(int v) { return (v & 1) != 0; }
 constexpr bool var_dbl(int v) { return (v & 4) != 0; }
 constexpr int row_scale(int v) { return (v >> 2) == 1 ? 1 : ((v >> 2) == 2 ? -1 : 0); }
+// column kernel: ids 8 and 9 are ids 0 and 1 with 4 elements per thread
+// (twice the threads, fewer registers per thread: for FP64)
+constexpr int col_e(int v) { return v >= 8 ? 4 : var_e(v); }
 // a row variant exists if each row has at least 2 threads; the doubled and
 // halved ones only where they really change the rows per block
 template <typename T, int M, int V> constexpr bool row_var_ok() {
@@ -216,18 +219,19 @@ template <typename T, int M, int V, int NF, int NFAM, int NC> struct ColLds {
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col_var_ok() {
-    if constexpr (V >= 8 || (V >= 4 && (V == 5 || V == 7 || M < 512))) return false;
-    else if constexpr (NC == 3 && V > 1) return false;  // off-plane: variants 0 and 1
-    else if constexpr (V >= 4) return M >= 2 * var_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
-    else if constexpr (NF == 1 && V != 0) return false;
+    if constexpr (V >= 10 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
+    else if constexpr (M / col_e(V) > 1024) return false;  // threads per block
+    else if constexpr (NC == 3 && V > 1 && V < 8) return false;  // off-plane: one column, E <= 8
+    else if constexpr (V >= 4 && V < 8) return M >= 2 * col_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
+    else if constexpr (NF == 1 && (V & 1)) return false;
     else if constexpr (M <= 256 && V > 1) return false;
-    else return M >= 2 * var_e(V) && ColLds<T, M, V, NF, NFAM, NC>::N * (int)sizeof(C<T>) <= 163840;
+    else return M >= 2 * col_e(V) && ColLds<T, M, V, NF, NFAM, NC>::N * (int)sizeof(C<T>) <= 163840;
 }
 
 template <typename T, int M, int V, int NF, int NFAM, int NC>
 __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                          const C<T> *__restrict__ ph) {
-    constexpr int E = var_e(V), NT = M / E, H = M / 2;
+    constexpr int E = col_e(V), NT = M / E, H = M / 2;
     const ColMap<M> map{col_region<M>()};
     __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
     const int t = threadIdx.x;
@@ -295,7 +299,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 template <typename T, int M, int V, int NF, int NFAM, int NC>
 __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
                                           const C<T> *__restrict__ ph) {
-    constexpr int E = var_e(V), NT = M / E, H = M / 2;
+    constexpr int E = col_e(V), NT = M / E, H = M / 2;
     const ColMap<M> map{col_region<M>()};
     __shared__ C<T> lds[2 * col_region<M>()];
     const int t = threadIdx.x;
@@ -356,7 +360,7 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
 }
 
 template <typename T, int M, int V, int NF, int NFAM, int NC>
-__global__ void __launch_bounds__((M / var_e(V)))
+__global__ void __launch_bounds__((M / col_e(V)))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
     if constexpr (var_dbl(V))
         col2_body<T, M, V, NF, NFAM, NC>(pk.a[blockIdx.z], tw, ph);
@@ -484,7 +488,7 @@ template <typename T, int M> struct Dispatch {
             return hipErrorInvalidValue;
         } else {
             const unsigned nblk = var_dbl(V) ? M / 4 : M / 2;
-            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, 1, n), dim3(M / var_e(V)), 0, s,
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, 1, n), dim3(M / col_e(V)), 0, s,
                                a, tw, ph);
             return hipGetLastError();
         }
@@ -514,6 +518,8 @@ template <typename T, int M> struct Dispatch {
             case 3: return col_nf<3>(a, n, nfields, nfam, ncomp, tw, ph, s);
             case 4: return col_nf<4>(a, n, nfields, nfam, ncomp, tw, ph, s);
             case 6: return col_nf<6>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 8: return col_nf<8>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 9: return col_nf<9>(a, n, nfields, nfam, ncomp, tw, ph, s);
         }
         return hipErrorInvalidValue;
     }
