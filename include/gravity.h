@@ -10,7 +10,9 @@
  *   F_x = G sum_i [ s_i K^{x,0}_i + dsx_i K^{x,x}_i + dsy_i K^{x,y}_i ]
  *
  * (and F_y likewise) with the exact cell-integrated kernels of Section 2 at
- * z = 0.  On a uniform grid this double sum is a discrete convolution
+ * z = 0; a plan with a height z != 0 gives (F_x, F_y, F_z) at that height
+ * above every zone centre (the kernels of Section 2 at general z).  On a
+ * uniform grid this double sum is a discrete convolution
  * (Section 4, the FFT form of the uniform-grid sum) and is evaluated by
  * zero-padded 2D FFTs, free of artificial boundary conditions.  On an AMR
  * grid (Section 3, Berger-Oliger refinement with leaf zones only) the same
@@ -20,7 +22,7 @@
  * are coarser leaves, whose centres are finest-lattice corners).
  *
  * Conventions
- *  - All array arguments of gravity_solve / gravity_solve_batch are DEVICE
+ *  - All array arguments of the solve calls are DEVICE
  *    pointers owned by the caller; they must stay valid until the work queued
  *    on `stream` has completed.  `stream` is a hipStream_t (NULL = the null
  *    stream).  Calls return once the work is queued.
@@ -184,7 +186,8 @@ gravity_status_t gravity_solve_profiled(gravity_plan_t plan, const void *sigma, 
                                         void *stream, int32_t reps, double *stage_ms,
                                         int32_t *nstages);
 
-/* Name of stage `stage` of this plan's pipeline ("" if out of range). */
+/* Name of stage `stage` of this plan's pipeline ("" if out of range):
+ * uniform plans "row_fwd", "col", "row_inv"; AMR plans add "gather". */
 const char *gravity_stage_name(gravity_plan_t plan, int32_t stage);
 
 /*
