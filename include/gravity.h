@@ -146,9 +146,9 @@ gravity_status_t gravity_solve(gravity_plan_t plan, const void *sigma, const voi
  * force at height z above every leaf centre, as gravity_solve with a third
  * composite-packed output fz (the vertical component; attraction towards
  * the disk).  Errors: as gravity_solve; EINVAL for a midplane plan (use
- * gravity_solve) or a NULL fz.  Off-plane plans are solved only through
- * this call (gravity_solve, the batch, the profiling call and the server
- * return EINVAL or EUNSUPPORTED for them).
+ * gravity_solve) or a NULL fz.  Off-plane plans are solved through this
+ * call, gravity_solve_batch_xyz and gravity_server_submit_xyz (the other
+ * solve calls and the profiling call return EINVAL or EUNSUPPORTED).
  */
 gravity_status_t gravity_solve_xyz(gravity_plan_t plan, const void *sigma, const void *dsx,
                                    const void *dsy, void *fx, void *fy, void *fz,
@@ -170,6 +170,17 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans,
                                      const void *const *sigma, const void *const *dsx,
                                      const void *const *dsy, void *const *fx,
                                      void *const *fy, void *workspace, void *stream);
+
+/*
+ * As gravity_solve_batch, for batches that include off-plane plans:
+ * fz holds n device pointers (entries of midplane plans are ignored and
+ * may be NULL).  Results are bit-identical to the single-solve calls.
+ */
+gravity_status_t gravity_solve_batch_xyz(int32_t n, const gravity_plan_t *plans,
+                                         const void *const *sigma, const void *const *dsx,
+                                         const void *const *dsy, void *const *fx,
+                                         void *const *fy, void *const *fz, void *workspace,
+                                         void *stream);
 
 /*
  * Profiling aid: queue one solve on `stream` as gravity_solve does, but
@@ -223,6 +234,10 @@ gravity_status_t gravity_server_create(size_t hbm_budget_bytes, int32_t nstreams
 gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t plan, const void *sigma,
                                        const void *dsx, const void *dsy, void *fx, void *fy,
                                        int64_t *ticket);
+/* As gravity_server_submit, with the third output fz of an off-plane plan. */
+gravity_status_t gravity_server_submit_xyz(gravity_server_t srv, gravity_plan_t plan,
+                                           const void *sigma, const void *dsx, const void *dsy,
+                                           void *fx, void *fy, void *fz, int64_t *ticket);
 /* *done = 1 once the ticket's solve has completed on the device. */
 gravity_status_t gravity_server_poll(gravity_server_t srv, int64_t ticket, int32_t *done);
 /* Block until the ticket completes; *latency_ms (optional) gets its latency. */

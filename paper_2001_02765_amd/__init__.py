@@ -28,8 +28,9 @@ _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5
 # exported symbols of include/gravity.h
 SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
            "gravity_solve", "gravity_solve_xyz", "gravity_batch_workspace_bytes", "gravity_solve_batch",
-           "gravity_solve_profiled", "gravity_stage_name", "gravity_server_create",
-           "gravity_server_submit", "gravity_server_poll", "gravity_server_wait",
+           "gravity_solve_batch_xyz", "gravity_solve_profiled", "gravity_stage_name",
+           "gravity_server_create", "gravity_server_submit", "gravity_server_submit_xyz",
+           "gravity_server_poll", "gravity_server_wait",
            "gravity_server_drain", "gravity_server_get_stats", "gravity_server_reset_stats",
            "gravity_server_destroy", "gravity_plan_destroy", "gravity_cache_bytes",
            "gravity_last_error")
@@ -71,6 +72,8 @@ _lib.gravity_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(_v
 _lib.gravity_batch_workspace_bytes.restype = ctypes.c_int
 _lib.gravity_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 5 + [_vp, _vp]
 _lib.gravity_solve_batch.restype = ctypes.c_int
+_lib.gravity_solve_batch_xyz.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 6 + [_vp, _vp]
+_lib.gravity_solve_batch_xyz.restype = ctypes.c_int
 _lib.gravity_solve_profiled.argtypes = [_vp] * 8 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                                     ctypes.POINTER(ctypes.c_int32)]
 _lib.gravity_solve_profiled.restype = ctypes.c_int
@@ -97,6 +100,8 @@ _lib.gravity_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c
 _lib.gravity_server_create.restype = ctypes.c_int
 _lib.gravity_server_submit.argtypes = [_vp] * 7 + [ctypes.POINTER(ctypes.c_int64)]
 _lib.gravity_server_submit.restype = ctypes.c_int
+_lib.gravity_server_submit_xyz.argtypes = [_vp] * 8 + [ctypes.POINTER(ctypes.c_int64)]
+_lib.gravity_server_submit_xyz.restype = ctypes.c_int
 _lib.gravity_server_poll.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
 _lib.gravity_server_poll.restype = ctypes.c_int
 _lib.gravity_server_wait.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
@@ -266,8 +271,9 @@ def batch_workspace_bytes(plans):
     return int(b.value)
 
 
-def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None):
-    """Queue independent solves as one batch (see gravity_solve_batch)."""
+def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None, fz=None):
+    """Queue independent solves as one batch (see gravity_solve_batch); fz:
+    third outputs, needed when the batch holds off-plane plans."""
     n = len(plans)
 
     def arr(ts):
@@ -276,8 +282,12 @@ def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None):
         return (_vp * max(1, n))(*[None if t is None else t.data_ptr() for t in ts])
 
     ph = (_vp * max(1, n))(*[p.handle for p in plans])
-    _check(_lib.gravity_solve_batch(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
-                                    _ptr(workspace), _stream_handle(stream)))
+    if fz is None:
+        _check(_lib.gravity_solve_batch(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
+                                        _ptr(workspace), _stream_handle(stream)))
+    else:
+        _check(_lib.gravity_solve_batch_xyz(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
+                                            arr(fz), _ptr(workspace), _stream_handle(stream)))
 
 
 class Server:
@@ -293,13 +303,19 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, plan, sigma, dsx, dsy, fx, fy):
-        """Queue a solve; tensors must stay alive until it completes (the
-        server keeps references until wait()).  Returns a ticket."""
+    def submit(self, plan, sigma, dsx, dsy, fx, fy, fz=None):
+        """Queue a solve (fz: third output of an off-plane plan); tensors must
+        stay alive until it completes (the server keeps references until
+        wait()).  Returns a ticket."""
         tk = ctypes.c_int64()
-        _check(_lib.gravity_server_submit(self._h, plan.handle, _ptr(sigma), _ptr(dsx), _ptr(dsy),
-                                          _ptr(fx), _ptr(fy), ctypes.byref(tk)))
-        self._keep[tk.value] = (plan, sigma, dsx, dsy, fx, fy)
+        if fz is None:
+            _check(_lib.gravity_server_submit(self._h, plan.handle, _ptr(sigma), _ptr(dsx), _ptr(dsy),
+                                              _ptr(fx), _ptr(fy), ctypes.byref(tk)))
+        else:
+            _check(_lib.gravity_server_submit_xyz(self._h, plan.handle, _ptr(sigma), _ptr(dsx),
+                                                  _ptr(dsy), _ptr(fx), _ptr(fy), _ptr(fz),
+                                                  ctypes.byref(tk)))
+        self._keep[tk.value] = (plan, sigma, dsx, dsy, fx, fy, fz)
         return tk.value
 
     def poll(self, ticket):

@@ -844,9 +844,11 @@ gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *
     });
 }
 
-gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
-                                     const void *const *dsx, const void *const *dsy, void *const *fx,
-                                     void *const *fy, void *workspace, void *stream) {
+// fz: NULL, or n pointers (entries of midplane plans ignored); off-plane
+// plans need theirs
+static gravity_status_t solve_batch(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
+                             const void *const *dsx, const void *const *dsy, void *const *fx,
+                             void *const *fy, void *const *fz, void *workspace, void *stream) {
     return guarded([&] {
         if (n < 0 || (n > 0 && (!plans || !sigma || !fx || !fy))) fail(GRAVITY_EINVAL, "bad batch arguments");
         std::vector<Item> items;
@@ -857,9 +859,14 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, con
             const void *dy = dsy ? dsy[i] : nullptr;
             char *ws = workspace ? (char *)workspace + off : nullptr;
             check_solve_args(plans[i], sigma[i], dx, dy, fx[i], fy[i], ws);
-            if (plans[i]->ncomp == 3)
-                fail(GRAVITY_EUNSUPPORTED, "off-plane plans are solved with gravity_solve_xyz");
-            items.push_back(Item{plans[i], sigma[i], dx, dy, fx[i], fy[i], ws});
+            void *z = nullptr;
+            if (plans[i]->ncomp == 3) {
+                if (!fz) fail(GRAVITY_EUNSUPPORTED, "off-plane plans need gravity_solve_batch_xyz");
+                z = fz[i];
+                if (!z || (((uintptr_t)z) & ((plans[i]->prec ? 16 : 8) - 1)))
+                    fail(GRAVITY_EINVAL, "off-plane solve needs an aligned fz");
+            }
+            items.push_back(Item{plans[i], sigma[i], dx, dy, fx[i], fy[i], ws, z});
             off += align256(plans[i]->ws_bytes);
         }
         // group solves that can share launches (stable order within a group)
@@ -879,6 +886,18 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, con
                 run_items(grp.data() + k, (int)std::min<size_t>(kPack, grp.size() - k), s);
         }
     });
+}
+
+gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
+                                     const void *const *dsx, const void *const *dsy, void *const *fx,
+                                     void *const *fy, void *workspace, void *stream) {
+    return solve_batch(n, plans, sigma, dsx, dsy, fx, fy, nullptr, workspace, stream);
+}
+
+gravity_status_t gravity_solve_batch_xyz(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
+                                         const void *const *dsx, const void *const *dsy, void *const *fx,
+                                         void *const *fy, void *const *fz, void *workspace, void *stream) {
+    return solve_batch(n, plans, sigma, dsx, dsy, fx, fy, fz, workspace, stream);
 }
 
 gravity_status_t gravity_solve_profiled(gravity_plan_t p, const void *sigma, const void *dsx,
@@ -1168,19 +1187,20 @@ gravity_status_t gravity_server_create(size_t budget, int32_t nstreams, int32_t 
     });
 }
 
-gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t p, const void *sigma,
-                                       const void *dsx, const void *dsy, void *fx, void *fy,
-                                       int64_t *ticket) {
+static gravity_status_t server_submit(gravity_server_t srv, gravity_plan_t p, const void *sigma, const void *dsx,
+                               const void *dsy, void *fx, void *fy, void *fz, int64_t *ticket) {
     return guarded([&] {
         if (!srv || !ticket) fail(GRAVITY_EINVAL, "NULL argument");
         alignas(256) static char aligned_dummy;
         check_solve_args(p, sigma, dsx, dsy, fx, fy, &aligned_dummy);
-        if (p->ncomp == 3) fail(GRAVITY_EUNSUPPORTED, "off-plane plans are solved with gravity_solve_xyz");
+        if (p->ncomp == 3 && !fz) fail(GRAVITY_EUNSUPPORTED, "off-plane plans need gravity_server_submit_xyz");
+        if (p->ncomp == 3 && (((uintptr_t)fz) & ((p->prec ? 16 : 8) - 1)))
+            fail(GRAVITY_EINVAL, "arrays must be aligned to two elements");
         if (p->device != srv->device) fail(GRAVITY_EINVAL, "plan and server are on different devices");
         const size_t ws = align256(p->ws_bytes);
         if (ws > srv->arena->size()) fail(GRAVITY_ENOMEM, "request workspace exceeds the server budget");
         SrvRequest r;
-        r.item = Item{p, sigma, dsx, dsy, fx, fy, nullptr};
+        r.item = Item{p, sigma, dsx, dsy, fx, fy, nullptr, p->ncomp == 3 ? fz : nullptr};
         r.ws_bytes = ws;
         r.t_submit = Clock::now();
         {
@@ -1194,6 +1214,18 @@ gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t p, c
         }
         srv->cv_work.notify_one();
     });
+}
+
+gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t p, const void *sigma,
+                                       const void *dsx, const void *dsy, void *fx, void *fy,
+                                       int64_t *ticket) {
+    return server_submit(srv, p, sigma, dsx, dsy, fx, fy, nullptr, ticket);
+}
+
+gravity_status_t gravity_server_submit_xyz(gravity_server_t srv, gravity_plan_t p, const void *sigma,
+                                           const void *dsx, const void *dsy, void *fx, void *fy, void *fz,
+                                           int64_t *ticket) {
+    return server_submit(srv, p, sigma, dsx, dsy, fx, fy, fz, ticket);
 }
 
 gravity_status_t gravity_server_poll(gravity_server_t srv, int64_t ticket, int32_t *done) {

@@ -489,6 +489,49 @@ def test_server_results_same_alone_and_in_mix(gl):
     srv.close()
 
 
+def test_offplane_batch_and_server_match_single_solves(gl):
+    """Off-plane plans in a batch (mixed with midplane ones) and through the
+    server give the bit-identical results of their single solves."""
+    rng = np.random.default_rng(21)
+    lay = diskgen.table10_layout()
+    plans = [gl.Plan(64, gl.F32, z=0.1), gl.Plan(64, gl.F32, z=0.1), gl.Plan(64, gl.F32),
+             gl.Plan(128, gl.F64, z=-0.05),
+             gl.Plan(lay.n0, gl.F64, x0=lay.x0, y0=lay.y0, h0=lay.h0, nlevels=lay.nlevels,
+                     patches=lay.patches, z=0.03)]
+    dts = ["f32", "f32", "f32", "f64", "f64"]
+    ins = [[_dev(rng.random(p.n_cells), d) for _ in range(3)] for p, d in zip(plans, dts)]
+    outs = [[torch.empty_like(v[0]) for _ in range(3)] for v in ins]
+    fz = [o[2] if p.ncomp == 3 else None for p, o in zip(plans, outs)]
+    ws = torch.empty(gl.batch_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    gl.solve_batch(plans, [v[0] for v in ins], [v[1] for v in ins], [v[2] for v in ins],
+                   [o[0] for o in outs], [o[1] for o in outs], ws, fz=fz)
+    torch.cuda.synchronize()
+    for p, v, o in zip(plans, ins, outs):
+        ref = p.solve_xyz(*v) if p.ncomp == 3 else p.solve(*v)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(ref, o))
+    srv = gl.Server(max(p.workspace_bytes for p in plans) * 2, nstreams=2, max_batch=4)
+    reqs = []
+    for i in range(20):
+        k = int(rng.integers(len(plans)))
+        p = plans[k]
+        vals = [_dev(rng.random(p.n_cells), dts[k]) for _ in range(3)]
+        o = [torch.empty_like(vals[0]) for _ in range(3)]
+        tk = srv.submit(p, *vals, o[0], o[1], o[2] if p.ncomp == 3 else None)
+        reqs.append((tk, p, vals, o))
+    for r in reqs:
+        srv.wait(r[0])
+    torch.cuda.synchronize()
+    for tk, p, vals, o in reqs:
+        ref = p.solve_xyz(*vals) if p.ncomp == 3 else p.solve(*vals)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(ref, o))
+    with pytest.raises(gl.GravityError) as e:
+        srv.submit(plans[0], *ins[0], outs[0][0], outs[0][1])   # off-plane without fz
+    assert e.value.status == gl.EUNSUPPORTED
+    srv.close()
+
+
 def test_server_rejects_oversized_request(gl):
     p = gl.Plan(128, gl.F32)
     srv = gl.Server(p.workspace_bytes // 2, nstreams=1)
