@@ -5,8 +5,11 @@ Workload (one step = one complete solve of the hot path): a uniform
 spiral disk exp(-r/0.25)(1 + 0.1 cos(2 theta - ln r / tan 20deg)) with 1%
 seeded Gaussian noise and central-difference slopes, inputs resident in HBM.
 The FP32 path is the headline value; the FP64 path, p50/p99 per-solve
-latency, the per-stage roofline of the dominant kernel and the CPU oracle's
-rate on a bounded sample are reported on the same JSON line.
+latency, the per-stage roofline of the dominant kernel, the whole-solve
+roofline under the compulsory and two-pass byte models, the spread over the
+disks of seeds 0-4, the AMR, off-plane, batched and served workloads (each
+beside the plain FP64 path) and the CPU oracle's rate on bounded samples are
+reported on the same JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -72,7 +75,7 @@ def stored_traffic(kernel, n):
     return None
 
 
-def run_precision(gl, torch, prec, n, steps, warmup, fields):
+def run_precision(gl, torch, prec, n, steps, warmup, fields, latency=True):
     dt = torch.float64 if prec == gl.F64 else torch.float32
     s, dx, dy, h = fields
     plan = gl.Plan(n, prec, h0=h)
@@ -90,6 +93,8 @@ def run_precision(gl, torch, prec, n, steps, warmup, fields):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / steps
+    if not latency:
+        return {"value": n * n / (ms * 1e-3), "ms_per_step": ms}
     # per-solve latency (one solve in flight), device events on the solve stream
     lat = []
     for _ in range(steps):
@@ -175,34 +180,47 @@ def batch_leg(gl, torch, reps):
         for p, i, o in zip(plans, ins, outs):
             p.solve(*i, fx=o[0], fy=o[1], workspace=ws1)
     ms_s = _timeit(torch, seq, reps)
+    # the plain FP64 path, one solve at a time, on the same disks
+    plans64 = [gl.Plan(n, gl.F64) for (n, _, _, _) in disks]
+    ins64 = [[a.double() for a in i] for i in ins]
+    outs64 = [(torch.empty_like(i[0]), torch.empty_like(i[0])) for i in ins64]
+    ws64 = torch.empty(max(p.workspace_bytes for p in plans64), dtype=torch.uint8, device="cuda")
+
+    def seq64():
+        for p, i, o in zip(plans64, ins64, outs64):
+            p.solve(*i, fx=o[0], fy=o[1], workspace=ws64)
+    ms_64 = _timeit(torch, seq64, reps)
     cells = int(sum(d[0] ** 2 for d in disks))
     return {"workload": "64 disks, n in {64..1024}, exponential/Kuzmin spirals, FP32",
-            "cells": cells, "ms_batch": ms_b, "ms_sequential": ms_s,
-            "forces_per_s_batch": cells / (ms_b * 1e-3), "forces_per_s_sequential": cells / (ms_s * 1e-3)}
+            "cells": cells, "ms_batch": ms_b, "ms_sequential": ms_s, "ms_sequential_f64": ms_64,
+            "forces_per_s_batch": cells / (ms_b * 1e-3), "forces_per_s_sequential": cells / (ms_s * 1e-3),
+            "forces_per_s_sequential_f64": cells / (ms_64 * 1e-3)}
 
 
-def serve_leg(gl, torch, nreq, rho=0.8, budget=8 << 30):
+def serve_leg(gl, torch, nreq, rhos=(0.5, 0.8), budget=8 << 30):
     """Poisson stream of AMR solves of mixed sizes through the continuous-
-    batching server: closed-loop capacity first, then arrivals at rho times it."""
+    batching server: closed-loop capacity first, then arrivals at rho times it
+    for each rho; beside it, the plain FP64 path solving the same layouts one
+    at a time."""
     import diskgen
-    pool = diskgen.request_pool(0, count=8)
+    pool = diskgen.request_pool(0, count=16)
     entries = []
     for lay, prof in pool:
         p = gl.Plan(lay.n0, gl.F32, nlevels=lay.nlevels, patches=lay.patches)
         s, dx, dy = lay.sample(prof)
         t = [torch.from_numpy(a).to("cuda", torch.float32) for a in (s, dx, dy)]
         outs = [(torch.empty_like(t[0]), torch.empty_like(t[0])) for _ in range(4)]
-        entries.append((p, t, outs))
+        entries.append((p, t, outs, lay))
     srv = gl.Server(budget, nstreams=4, max_batch=8)
     rng = np.random.default_rng(1)
     picks = rng.integers(len(entries), size=nreq)
 
     def submit(k):
-        p, t, outs = entries[picks[k]]
+        p, t, outs, _ = entries[picks[k]]
         o = outs[k % len(outs)]
         return srv.submit(p, *t, o[0], o[1])
 
-    for k in range(min(16, nreq)):  # warm-up
+    for k in range(min(200, nreq)):  # warm-up
         submit(k)
     srv.drain()
     srv.reset_stats()
@@ -212,31 +230,54 @@ def serve_leg(gl, torch, nreq, rho=0.8, budget=8 << 30):
     srv.drain()
     cap = nreq / (time.perf_counter() - t0)
     closed = srv.stats()
-    srv.reset_stats()
-    lam = rho * cap
-    gaps = rng.exponential(1.0 / lam, size=nreq)
-    t_arr = time.perf_counter() + np.cumsum(gaps)
-    t0 = time.perf_counter()
-    for k in range(nreq):
-        while time.perf_counter() < t_arr[k]:
-            pass
-        submit(k)
-    srv.drain()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    leaves = st["leaves_completed"]
+    runs = []
+    for rho in rhos:
+        srv.reset_stats()
+        lam = rho * cap
+        gaps = rng.exponential(1.0 / lam, size=nreq)
+        t_arr = time.perf_counter() + np.cumsum(gaps)
+        t0 = time.perf_counter()
+        for k in range(nreq):
+            while time.perf_counter() < t_arr[k]:
+                pass
+            submit(k)
+        srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        runs.append({"rho": rho, "rate_req_per_s": lam, "p50_ms": st["latency_p50_ms"],
+                     "p99_ms": st["latency_p99_ms"], "max_ms": st["latency_max_ms"],
+                     "leaf_forces_per_s": st["leaves_completed"] / wall,
+                     "peak_bytes_in_use": st["peak_bytes_in_use"], "batches": st["batches"]})
+    budget_bytes = srv.stats()["budget_bytes"]
     srv.close()
-    return {"workload": "Poisson arrivals of AMR solves (base 128^2-2048^2, 1-3 levels, "
-                        "4-256 patches, finest lattice <= 4096^2), FP32, 8 distinct layouts",
-            "requests": nreq, "capacity_req_per_s": cap, "rate_req_per_s": lam,
-            "p50_ms": st["latency_p50_ms"], "p99_ms": st["latency_p99_ms"],
-            "max_ms": st["latency_max_ms"], "leaf_forces_per_s": leaves / wall,
+    # plain FP64 single solves of the same request mix (one stream, one at a
+    # time): each layout timed alone, weighted by how often the stream asked for it
+    weights = np.bincount(picks, minlength=len(entries))
+    leaves = ms = 0.0
+    for (_, t, _, lay), w in zip(entries, weights):
+        p = gl.Plan(lay.n0, gl.F64, nlevels=lay.nlevels, patches=lay.patches)
+        t64 = [a.double() for a in t]
+        f = (torch.empty_like(t64[0]), torch.empty_like(t64[0]))
+        ws = p.workspace()
+        m = _timeit(torch, lambda: p.solve(*t64, fx=f[0], fy=f[1], workspace=ws), 5)
+        leaves += p.n_leaves * float(w)
+        ms += m * float(w)
+        del p, t64, f, ws
+    levels = sorted({lay.nlevels for *_, lay in entries})
+    bases = sorted({lay.n0 for *_, lay in entries})
+    npat = [len(lay.patches) for *_, lay in entries if lay.nlevels > 1]
+    finest = max(lay.n0 << (lay.nlevels - 1) for *_, lay in entries)
+    return {"workload": "Poisson arrivals of AMR solves over %d seeded layouts (bases %s, levels %s, "
+                        "%s patches of 32^2 per refined layout, finest lattice up to %d^2), FP32"
+                        % (len(entries), "/".join(map(str, bases)), "/".join(map(str, levels)),
+                           ("%d-%d" % (min(npat), max(npat))) if npat else "no", finest),
+            "requests": nreq, "warmup_requests": min(200, nreq), "capacity_req_per_s": cap,
             "closed_loop_p50_ms": closed["latency_p50_ms"], "closed_loop_p99_ms": closed["latency_p99_ms"],
-            "budget_bytes": st["budget_bytes"], "peak_bytes_in_use": st["peak_bytes_in_use"],
-            "batches": st["batches"]}
+            "budget_bytes": budget_bytes, "open_loop": runs,
+            "plain_f64_leaf_forces_per_s": leaves / (ms * 1e-3)}
 
 
-def cpu_baseline(n, fields, budget_s=25.0):
+def cpu_baseline(n, fields, budget_s=25.0, with_amr=True):
     """The oracle's direct leaf sum (exact kernels per source cell, FP64,
     compensated) on a seeded sample of target cells of the same workload,
     every source included.  Returns forces/s and the thread count."""
@@ -262,10 +303,68 @@ def cpu_baseline(n, fields, budget_s=25.0):
     t1 = time.perf_counter()
     oracle.direct(lay_rect, s.ravel(), dx.ravel(), dy.ravel(), cent[tg1], threads=1)
     el1 = time.perf_counter() - t1
+    amr = cpu_baseline_amr(threads, budget_s / 3) if with_amr else None
     return {"value": k / el, "unit": "forces/s", "cores": threads, "kind": "oracle",
             "sample": "%d seeded target cells of the %dx%d disk, each summed over all %d source "
                       "cells with the exact kernels (direct method), %.1f s" % (k, n, n, n * n, el),
-            "value_1core": 4 / el1, "sample_1core": "4 target cells on one thread, %.1f s" % el1}
+            "value_1core": 4 / el1, "sample_1core": "4 target cells on one thread, %.1f s" % el1,
+            **({"amr": amr} if amr else {})}
+
+
+def cpu_baseline_amr(threads, budget_s):
+    """The oracle's direct leaf sum on the 3-level AMR workload: seeded
+    targets drawn equally from the leaves of each level, every leaf a
+    source.  Returns leaf forces/s."""
+    import diskgen
+    import oracle
+
+    lay, s, dx, dy = diskgen.amr_config(0)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    width = rect[:, 1] - rect[:, 0]
+    levels = np.unique(width)
+    rng = np.random.default_rng(11)
+
+    def timed(per_level):
+        tg = np.concatenate([rng.choice(np.nonzero(width == w)[0], min(per_level, int(np.sum(width == w))),
+                                        replace=False) for w in levels])
+        t0 = time.perf_counter()
+        oracle.direct(rect, s[idx], dx[idx], dy[idx], cent[tg], threads=threads)
+        return len(tg), time.perf_counter() - t0
+
+    k0, e0 = timed(max(1, threads // len(levels)))
+    per = int(max(1, min(2048 // len(levels), k0 / len(levels) * budget_s / max(e0, 1e-3))))
+    k, el = timed(per)
+    return {"value": k / el, "unit": "leaf forces/s",
+            "sample": "%d seeded leaf targets (%d per level, %d levels) of the 3-level AMR workload, "
+                      "each summed over all %d leaves, %.1f s" % (k, per, len(levels), len(idx), el)}
+
+
+def seed_spread(gl, torch, n, steps, warmup, first):
+    """FP32 forces/s of the headline solve on the disks of seeds 0-4 (seed 0
+    is the main run): median and spread."""
+    import diskgen
+    vals = [first]
+    for seed in range(1, 5):
+        r = run_precision(gl, torch, gl.F32, n, steps, warmup, diskgen.noisy_spiral(n, seed),
+                          latency=False)
+        vals.append(r["value"])
+    return {"seeds": list(range(5)), "forces_per_s": vals, "median": float(np.median(vals)),
+            "min": float(min(vals)), "max": float(max(vals))}
+
+
+def solve_roofline(n, ms32, ms64):
+    """Whole-solve HBM roofline under two byte models per leaf (slopes on):
+    compulsory (three fields in, two forces out, six real-quadrant kernel
+    spectra read once: 44 B in FP32) and two passes out of cache (row
+    forward, fused column pass, row inverse, each streaming its spectra
+    through HBM once: 124 B in FP32); FP64 doubles both."""
+    out = {}
+    for name, ms, k in (("f32", ms32, 1), ("f64", ms64, 2)):
+        bmin, b2 = 44 * k * n * n, 124 * k * n * n
+        out[name] = {"ms": ms, "bytes_compulsory": bmin, "bytes_two_pass": b2,
+                     "frac_compulsory": bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "frac_two_pass": b2 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def copy_gbs(torch, nbytes=1 << 30, reps=10):
@@ -368,14 +467,16 @@ def main():
         "variants": r32["variants"],
         "fp64": r64,
         "roofline": roof,
+        "solve_roofline": solve_roofline(n, r32["ms_per_step"], r64["ms_per_step"]),
     }
     if not args.no_extra:
+        out["seed_spread"] = seed_spread(gl, torch, n, max(20, args.steps // 2), args.warmup, r32["value"])
         out["amr"] = amr_leg(gl, torch, max(10, args.steps // 4))
         out["offplane"] = offplane_leg(gl, torch, max(10, args.steps // 4), fields, n)
         out["batch"] = batch_leg(gl, torch, max(5, args.steps // 20))
-        out["serve"] = serve_leg(gl, torch, nreq=max(100, 2 * args.steps))
+        out["serve"] = serve_leg(gl, torch, nreq=max(200, 10 * args.steps))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, fields)
+        out["cpu_baseline"] = cpu_baseline(n, fields, with_amr=not args.no_extra)
     print(json.dumps(out), flush=True)
 
 
