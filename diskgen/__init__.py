@@ -177,20 +177,24 @@ class Layout:
         """Blocks in composite-packed order with their leaf masks."""
         out = []
         rects = [Patch(0, 0, 0, self.n0, self.n0)] + list(self.patches)
+        # child footprints per level, in the parent level's cell index (ratio 2)
+        foot = {}
+        for c in self.patches:
+            foot.setdefault(c.level, []).append((c.i0 // 2, c.j0 // 2, (c.i0 + c.nx + 1) // 2,
+                                                 (c.j0 + c.ny + 1) // 2))
+        foot = {l: np.array(v, dtype=np.int64) for l, v in foot.items()}
         off = 0
         for b in rects:
             h = self.h(b.level)
             mask = np.ones((b.ny, b.nx), dtype=bool)
-            for c in self.patches:
-                if c.level != b.level + 1:
-                    continue
-                # child footprint in this level's index (ratio 2)
-                ci0, cj0 = c.i0 // 2, c.j0 // 2
-                ci1, cj1 = (c.i0 + c.nx + 1) // 2, (c.j0 + c.ny + 1) // 2
-                a0, a1 = max(ci0, b.i0), min(ci1, b.i0 + b.nx)
-                c0, c1 = max(cj0, b.j0), min(cj1, b.j0 + b.ny)
-                if a0 < a1 and c0 < c1:
-                    mask[c0 - b.j0:c1 - b.j0, a0 - b.i0:a1 - b.i0] = False
+            f = foot.get(b.level + 1)
+            if f is not None:
+                a0 = np.maximum(f[:, 0], b.i0)
+                a1 = np.minimum(f[:, 2], b.i0 + b.nx)
+                c0 = np.maximum(f[:, 1], b.j0)
+                c1 = np.minimum(f[:, 3], b.j0 + b.ny)
+                for k in np.nonzero((a0 < a1) & (c0 < c1))[0]:
+                    mask[c0[k] - b.j0:c1[k] - b.j0, a0[k] - b.i0:a1[k] - b.i0] = False
             out.append(Block(b.level, b.i0, b.j0, b.nx, b.ny, self.x0 + b.i0 * h,
                              self.y0 + b.j0 * h, h, off, mask))
             off += b.nx * b.ny
@@ -284,6 +288,72 @@ def flag_layout(profile, n0, nlevels, tile=16, thresh=0.1, x0=-1.0, y0=-1.0, h0=
         if not new:
             break
     return Layout(n0, nlevels, patches, x0, y0, h0)
+
+
+def band_layout(n0, nlevels, centres, alpha, widths, x0=-1.0, y0=-1.0, h0=None):
+    """Refinement around the edges of disks of radius ``alpha`` about each of
+    ``centres`` (the D2 and D2,2 experiments of Section 3): every cell of level
+    l (0 = base; at l >= 1 only cells that exist, i.e. children of refined
+    cells) whose centre lies closer than ``widths[l]`` to one of the circles
+    is split into 2 x 2 children.  Each run of consecutive refined cells along
+    a row becomes one patch of 2 x 2k children, so the patches of a level are
+    disjoint and nested in the level below."""
+    if h0 is None:
+        h0 = 2.0 / n0
+    patches = []
+    exists = np.ones((n0, n0), dtype=bool)
+    for lvl in range(nlevels - 1):
+        n = n0 << lvl
+        h = h0 / 2 ** lvl
+        c = (np.arange(n) + 0.5) * h
+        X, Y = np.meshgrid(x0 + c, y0 + c)
+        d = np.full((n, n), np.inf)
+        for cx, cy in centres:
+            d = np.minimum(d, np.abs(np.hypot(X - cx, Y - cy) - alpha))
+        flag = exists & (d < widths[lvl])
+        del X, Y, d
+        if not flag.any():
+            break
+        # runs of flagged cells along each row
+        pad = np.zeros((n, 1), dtype=np.int8)
+        edges = np.diff(np.concatenate([pad, flag.astype(np.int8), pad], axis=1), axis=1)
+        rs, cs = np.nonzero(edges == 1)
+        re, ce = np.nonzero(edges == -1)
+        for j, i0, i1 in zip(rs, cs, ce):
+            patches.append(Patch(lvl + 1, 2 * int(i0), 2 * int(j), 2 * int(i1 - i0), 2))
+        exists = np.repeat(np.repeat(flag, 2, axis=0), 2, axis=1)
+    return Layout(n0, nlevels, patches, x0, y0, h0)
+
+
+def disk_centres(disk):
+    """Centres of the D2 components: one disk at the origin (D2) or two at
+    (0, +-0.5) (D2,2)."""
+    return [(0.0, 0.0)] if disk == "d2" else [(0.0, 0.5), (0.0, -0.5)]
+
+
+def _band_scale(disk):
+    # the zone counts of the D2,2 experiments fit bands 0.8 times as wide as
+    # those of D2 (equivalently, the D2 bands about circles of radius 0.2)
+    return 1.0 if disk == "d2" else 0.8
+
+
+def ilr_layout(n0, nlevels, disk="d2", alpha=0.25):
+    """Independent level refinement (Section 3; reading): cells within 0.05
+    of the disk edge are refined at the base level, within 0.025 at the next,
+    the same physical band for every base size."""
+    k = _band_scale(disk)
+    return band_layout(n0, nlevels, disk_centres(disk), alpha,
+                       [k * 0.05 / 2 ** l for l in range(nlevels)])
+
+
+def vlr_layout(n0, nlevels, disk="d2", alpha=0.25):
+    """Variable level refinement (Section 3; reading): the band is 12.8 cells
+    of the level being refined (0.2 at a 128^2 base), so it narrows with
+    every doubling of the base and with every level."""
+    k = _band_scale(disk)
+    h0 = 2.0 / n0
+    return band_layout(n0, nlevels, disk_centres(disk), alpha,
+                       [k * 12.8 * h0 / 2 ** l for l in range(nlevels)])
 
 
 def clumps(seed, n=8, rmax=0.7):

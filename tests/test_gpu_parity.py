@@ -227,6 +227,43 @@ def test_amr_config3_sampled(gl, prec):
     assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind,disk", [("ilr", "d2"), ("vlr", "d22")])
+def test_band_layouts_sampled(gl, prec, kind, disk):
+    """The refinement layouts of the Section 3 experiments (3 levels, base
+    128^2, hundreds of 2-row patches): leaf targets sampled on every level,
+    and in the band about the disk edge, against the leaf direct sum."""
+    gen = diskgen.ilr_layout if kind == "ilr" else diskgen.vlr_layout
+    lay = gen(128, 3, disk)
+    assert len(lay.patches) > 150
+    s, dx, dy = lay.sample(diskgen.d2 if disk == "d2" else diskgen.d22)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    size = rect[:, 1] - rect[:, 0]
+    rng = np.random.default_rng(13)
+    sel = []
+    for hv in np.unique(size):
+        cand = np.nonzero(size == hv)[0]
+        sel.extend(rng.choice(cand, min(16, len(cand)), replace=False))
+    sel = np.array(sorted(sel))
+    assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
+
+
+def test_ilr_d2_accuracy_and_order(gl):
+    """AMR(2, D2) under ILR (Section 3, Table 3): against the analytic force
+    the errors fall at second order in L1 and L2 from N_k = 128 to 256, and
+    at each size they are below those of the uniform base grid."""
+    import amr_study
+    rows = [amr_study.run_case(gl, torch, "ilr", "d2", 2, n) for n in (128, 256)]
+    uni = [amr_study.run_case(gl, torch, "ilr", "d2", 1, n) for n in (128, 256)]
+    for r, u in zip(rows, uni):
+        for c in ("x", "R"):
+            assert r["norms"][c][0] < u["norms"][c][0]
+            assert r["norms"][c][1] < u["norms"][c][1]
+    o = amr_study.orders(rows)[0]
+    assert o["x"][0] > 1.8 and o["R"][0] > 1.8
+    assert o["x"][1] > 1.7 and o["R"][1] > 1.7
+
+
 # ---------------------------------------------------------------------------
 # off-plane targets (Section 2 at z != 0): (Fx, Fy, Fz) at height z
 # ---------------------------------------------------------------------------
