@@ -249,13 +249,33 @@ template <int L, int NT> struct PassInfo<L, NT, 0> {
     static constexpr int NS = 1;
 };
 
+// Compact twiddles: transforms of length 4096 and more keep only the base
+// twiddle w = e^{-2 pi i k / (NS R)} of each butterfly group and form its
+// powers w^r by products at use (w^r = w^{r/2} w^{r - r/2}, at most log2 R
+// products deep).  The base twiddle passes through an empty volatile asm at
+// each use, so that the compiler cannot keep the products of one transform
+// alive for the next.  Storing all R - 1 powers made the column kernels at
+// these lengths, whose blocks of M/E threads leave at most 256 (1024
+// threads: 128) registers per lane, spill to scratch memory.
+template <int L> constexpr bool tw_compact() { return L >= 4096; }
+
+// twiddle registers (complex) of one pass: R - 1 powers per butterfly
+// group, or the base twiddle only (compact); none for the first pass
+template <int L, int NT, int P> constexpr int tw_pass_count() {
+    using PI = PassInfo<L, NT, P>;
+    return PI::NS > 1 ? PI::B * (tw_compact<L>() ? 1 : PI::R - 1) : 0;
+}
+
 // number of complex twiddle registers needed by passes [P, npass)
 template <int L, int NT, int P> constexpr int tw_count() {
     if constexpr (P >= Plan<L, NT>::npass) return 0;
-    else {
-        using PI = PassInfo<L, NT, P>;
-        return (PI::NS > 1 ? PI::B * (PI::R - 1) : 0) + tw_count<L, NT, P + 1>();
-    }
+    else return tw_pass_count<L, NT, P>() + tw_count<L, NT, P + 1>();
+}
+
+// p[r] = w^r for r in [1, R), from p[1] = w
+template <typename T, int R> __device__ __forceinline__ void tw_powers(C<T> *p) {
+#pragma unroll
+    for (int r = 2; r < R; ++r) p[r] = cmul<T>(p[r >> 1], p[r - (r >> 1)]);
 }
 
 template <typename T, int L, int NT> struct TwReg {
@@ -267,14 +287,18 @@ template <typename T, int L, int NT> struct TwReg {
         if constexpr (P < Plan<L, NT>::npass) {
             using PI = PassInfo<L, NT, P>;
             constexpr int NS = PI::NS, R = PI::R, B = PI::B;
-            constexpr int CNT = (NS > 1) ? B * (R - 1) : 0;
+            constexpr int CNT = tw_pass_count<L, NT, P>();
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const int k = (t + NT * b) & (NS - 1);
+                    if constexpr (tw_compact<L>()) {
+                        w[OFF + b] = tw[(k * (L / (NS * R))) * tws];
+                    } else {
 #pragma unroll
-                    for (int r = 1; r < R; ++r)
-                        w[OFF + b * (R - 1) + (r - 1)] = tw[(r * k * (L / (NS * R))) * tws];
+                        for (int r = 1; r < R; ++r)
+                            w[OFF + b * (R - 1) + (r - 1)] = tw[(r * k * (L / (NS * R))) * tws];
+                    }
                 }
             }
             load_pass<P + 1, OFF + CNT>(tw, tws, t);
@@ -320,11 +344,17 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP 
     using PI = PassInfo<L, NT, P>;
     constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
     constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
-    constexpr int CNT = (NS > 1) ? B * (R - 1) : 0;
+    constexpr int CNT = tw_pass_count<L, NT, P>();
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + NT * b;
         const int k = j & (NS - 1);
+        C<T> pw[R];  // compact twiddles: the powers of this group's base twiddle
+        if constexpr (NS > 1 && tw_compact<L>()) {
+            pw[1] = tr.w[OFF + b];
+            asm volatile("" : "+v"(pw[1].x), "+v"(pw[1].y));
+            tw_powers<T, R>(pw);
+        }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             C<T> v[R];
@@ -332,7 +362,8 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP 
             for (int r = 0; r < R; ++r) v[r] = reg[i][b + r * B];
             if constexpr (NS > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[r] = twm<DIR, T>(v[r], tr.w[OFF + b * (R - 1) + (r - 1)]);
+                for (int r = 1; r < R; ++r)
+                    v[r] = twm<DIR, T>(v[r], tw_compact<L>() ? pw[r] : tr.w[OFF + b * (R - 1) + (r - 1)]);
             }
             dft<R, DIR, T>(v);
             if constexpr (LAST) {

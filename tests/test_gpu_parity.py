@@ -248,6 +248,25 @@ def test_band_layouts_sampled(gl, prec, kind, disk):
     assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n0,levels", [(1024, 2), (1024, 3)])
+def test_amr_large_lattices_sampled(gl, prec, n0, levels):
+    """AMR at the largest transform sizes (finest lattice 2048^2 and 4096^2,
+    FFTs of 4096 and 8192 points per side): ILR layouts of the D2 disk, leaf
+    targets sampled on every level against the leaf direct sum."""
+    lay = diskgen.ilr_layout(n0, levels, "d2")
+    s, dx, dy = lay.sample(diskgen.d2)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    size = rect[:, 1] - rect[:, 0]
+    rng = np.random.default_rng(17)
+    sel = []
+    for hv in np.unique(size):
+        cand = np.nonzero(size == hv)[0]
+        sel.extend(rng.choice(cand, min(8, len(cand)), replace=False))
+    sel = np.array(sorted(sel))
+    assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
+
+
 def test_ilr_d2_accuracy_and_order(gl):
     """AMR(2, D2) under ILR (Section 3, Table 3): against the analytic force
     the errors fall at second order in L1 and L2 from N_k = 128 to 256, and
