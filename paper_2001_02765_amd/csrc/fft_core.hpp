@@ -249,15 +249,17 @@ template <int L, int NT> struct PassInfo<L, NT, 0> {
     static constexpr int NS = 1;
 };
 
-// Compact twiddles: transforms of length 4096 and more keep only the base
+// Compact twiddles: transforms of length 1024 and more keep only the base
 // twiddle w = e^{-2 pi i k / (NS R)} of each butterfly group and form its
 // powers w^r by products at use (w^r = w^{r/2} w^{r - r/2}, at most log2 R
 // products deep).  The base twiddle passes through an empty volatile asm at
 // each use, so that the compiler cannot keep the products of one transform
-// alive for the next.  Storing all R - 1 powers made the column kernels at
-// these lengths, whose blocks of M/E threads leave at most 256 (1024
-// threads: 128) registers per lane, spill to scratch memory.
-template <int L> constexpr bool tw_compact() { return L >= 4096; }
+// alive for the next.  Holding all R - 1 powers in registers made the column
+// kernels from 4096 points on (blocks of M/E threads leave at most 256, at
+// 1024 threads 128, registers per lane) spill to scratch memory; at 1024 and
+// 2048 points the smaller register footprint alone measured 10-15% faster
+// (column and row kernels of the 1024^2 solve), below 1024 it is neutral.
+template <int L> constexpr bool tw_compact() { return L >= 1024; }
 
 // twiddle registers (complex) of one pass: R - 1 powers per butterfly
 // group, or the base twiddle only (compact); none for the first pass
