@@ -136,6 +136,27 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _check_cells(t, dtype, n, what, required=True):
+    """The C ABI takes plain device pointers and cannot see sizes: every
+    array handed to it is checked here (dtype, device, contiguity, length)."""
+    if t is None:
+        if required:
+            raise ValueError("%s is required" % what)
+        return
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s CUDA tensor" % (what, dtype))
+    if t.numel() != n:
+        raise ValueError("%s must hold %d composite-packed cells, not %d" % (what, n, t.numel()))
+
+
+def _check_workspace(ws, nbytes):
+    if ws is None or not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    if ws.numel() * ws.element_size() < nbytes:
+        raise ValueError("workspace holds %d bytes, the solve needs %d"
+                         % (ws.numel() * ws.element_size(), nbytes))
+
+
 def _stream_handle(stream):
     import torch
     if stream is None:
@@ -203,6 +224,16 @@ class Plan:
         except Exception:
             pass
 
+    def _check_inputs(self, sigma, dsx, dsy):
+        _check_cells(sigma, self.torch_dtype, self.n_cells, "sigma")
+        _check_cells(dsx, self.torch_dtype, self.n_cells, "dsx", required=False)
+        _check_cells(dsy, self.torch_dtype, self.n_cells, "dsy", required=False)
+
+    def _check_outputs(self, outs, workspace):
+        for name, o in zip(("fx", "fy", "fz"), outs):
+            _check_cells(o, self.torch_dtype, self.n_cells, name)
+        _check_workspace(workspace, self.workspace_bytes)
+
     def workspace(self):
         """A fresh device workspace tensor of the required size."""
         import torch
@@ -215,17 +246,14 @@ class Plan:
         (fx, fy), allocated if not given."""
         import torch
         dt = self.torch_dtype
-        for t in (sigma, dsx, dsy):
-            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
-                raise ValueError("inputs must be contiguous %s CUDA tensors" % dt)
-            if t is not None and t.numel() != self.n_cells:
-                raise ValueError("inputs must hold %d composite-packed cells" % self.n_cells)
+        self._check_inputs(sigma, dsx, dsy)
         if fx is None:
             fx = torch.empty(self.n_cells, dtype=dt, device=sigma.device)
         if fy is None:
             fy = torch.empty(self.n_cells, dtype=dt, device=sigma.device)
         if workspace is None:
             workspace = self.workspace()
+        self._check_outputs((fx, fy), workspace)
         _check(_lib.gravity_solve(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx), _ptr(fy),
                                   _ptr(workspace), _stream_handle(stream)))
         return fx, fy
@@ -237,15 +265,12 @@ class Plan:
         every leaf centre; returns (fx, fy, fz), allocated if not given."""
         import torch
         dt = self.torch_dtype
-        for t in (sigma, dsx, dsy):
-            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
-                raise ValueError("inputs must be contiguous %s CUDA tensors" % dt)
-            if t is not None and t.numel() != self.n_cells:
-                raise ValueError("inputs must hold %d composite-packed cells" % self.n_cells)
+        self._check_inputs(sigma, dsx, dsy)
         out = [o if o is not None else torch.empty(self.n_cells, dtype=dt, device=sigma.device)
                for o in (fx, fy, fz)]
         if workspace is None:
             workspace = self.workspace()
+        self._check_outputs(out, workspace)
         _check(_lib.gravity_solve_xyz(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(out[0]),
                                       _ptr(out[1]), _ptr(out[2]), _ptr(workspace),
                                       _stream_handle(stream)))
@@ -255,6 +280,8 @@ class Plan:
         """Mean device milliseconds of one launch of each pipeline stage, each
         stage launched ``reps`` times back to back between HIP events on the
         solve stream: {stage name: ms}."""
+        self._check_inputs(sigma, dsx, dsy)
+        self._check_outputs((fx, fy), workspace)
         ms = (ctypes.c_double * 8)()
         ns = ctypes.c_int32()
         _check(_lib.gravity_solve_profiled(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx),
@@ -281,6 +308,14 @@ def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None, fz=None)
             return None
         return (_vp * max(1, n))(*[None if t is None else t.data_ptr() for t in ts])
 
+    for k, p in enumerate(plans):
+        p._check_inputs(sigma[k], None if dsx is None else dsx[k], None if dsy is None else dsy[k])
+        for name, o in (("fx", fx), ("fy", fy), ("fz", fz)):
+            # a missing fz is the library's to reject (off-plane plan in a midplane call)
+            if o is not None or name != "fz":
+                _check_cells(None if o is None else o[k], p.torch_dtype, p.n_cells,
+                             "%s[%d]" % (name, k), required=(name != "fz"))
+    _check_workspace(workspace, batch_workspace_bytes(plans))
     ph = (_vp * max(1, n))(*[p.handle for p in plans])
     if fz is None:
         _check(_lib.gravity_solve_batch(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
@@ -307,6 +342,10 @@ class Server:
         """Queue a solve (fz: third output of an off-plane plan); tensors must
         stay alive until it completes (the server keeps references until
         wait()).  Returns a ticket."""
+        plan._check_inputs(sigma, dsx, dsy)
+        for name, o in (("fx", fx), ("fy", fy)):
+            _check_cells(o, plan.torch_dtype, plan.n_cells, name)
+        _check_cells(fz, plan.torch_dtype, plan.n_cells, "fz", required=False)
         tk = ctypes.c_int64()
         if fz is None:
             _check(_lib.gravity_server_submit(self._h, plan.handle, _ptr(sigma), _ptr(dsx), _ptr(dsy),

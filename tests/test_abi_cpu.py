@@ -57,3 +57,18 @@ def test_null_arguments(gl):
     assert gl._lib.gravity_plan(None, None) == gl.EINVAL
     assert gl._lib.gravity_batch_workspace_bytes(-1, None, ctypes.byref(b)) == gl.EINVAL
     gl._lib.gravity_plan_destroy(None)
+
+
+def test_binding_checks_sizes_before_calling_the_library():
+    """The C ABI takes plain pointers, so the binding checks every array it
+    hands over: dtype, device, contiguity and length (CPU tensors here are
+    rejected before any device call)."""
+    import torch
+    import paper_2001_02765_amd as gl
+    with pytest.raises(ValueError, match="CUDA"):
+        gl._check_cells(torch.zeros(16), torch.float32, 16, "fx")
+    with pytest.raises(ValueError, match="required"):
+        gl._check_cells(None, torch.float32, 16, "fx")
+    gl._check_cells(None, torch.float32, 16, "dsx", required=False)
+    with pytest.raises(ValueError, match="workspace"):
+        gl._check_workspace(torch.zeros(16, dtype=torch.uint8), 8)

@@ -503,6 +503,14 @@ def test_invalid_requests(gl):
     with pytest.raises(gl.GravityError) as e:
         p.solve(s, None, None)  # slopes missing
     assert e.value.status == gl.EINVAL
+    # arrays the library cannot size-check are checked by the binding
+    with pytest.raises(ValueError, match="fx"):
+        p.solve(s, s, s, fx=torch.empty(32 * 31, device="cuda"))
+    with pytest.raises(ValueError, match="workspace"):
+        p.solve(s, s, s, workspace=torch.empty(max(1, p.workspace_bytes // 2), dtype=torch.uint8,
+                                               device="cuda"))
+    with pytest.raises(ValueError, match="sigma"):
+        p.solve(s.double(), s, s)
 
 
 def test_server_results_same_alone_and_in_mix(gl):
