@@ -145,6 +145,30 @@ def amr_leg(gl, torch, reps):
     return out
 
 
+def paper_amr_leg(gl, torch, reps):
+    """The largest AMR experiment of the paper's Section 3 that this path
+    runs: AMR(3, D2) under independent level refinement at N_k = 1024 (1.42M
+    leaves, finest lattice 4096^2, 8192^2 FFT), FP32 and FP64.  Table 8
+    times the same case with the direct sum on a P100 at 1.05e3 s (context:
+    another algorithm on other hardware)."""
+    import diskgen
+    lay = diskgen.ilr_layout(1024, 3, "d2")
+    s, dx, dy = lay.sample(diskgen.d2)
+    out = {"workload": "AMR(3, D2) ILR, N_k = 1024: %d leaves in %d patches, finest lattice %d^2"
+                       % (lay.nleaves(), len(lay.patches), lay.n_finest),
+           "leaves": lay.nleaves(), "paper_p100_direct_s": 1.05e3}
+    for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
+        p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches)
+        t = [torch.from_numpy(a).to("cuda", dt) for a in (s, dx, dy)]
+        fx = torch.empty(p.n_cells, dtype=dt, device="cuda")
+        fy = torch.empty_like(fx)
+        ws = p.workspace()
+        ms = _timeit(torch, lambda: p.solve(*t, fx=fx, fy=fy, workspace=ws), reps)
+        out[name] = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3)}
+        del p, t, fx, fy, ws
+    return out
+
+
 def offplane_leg(gl, torch, reps, fields, n):
     """The headline disk with targets at height z = 0.05 above every cell
     centre (25.6 cells at 1024^2): (Fx, Fy, Fz) per cell."""
@@ -472,6 +496,7 @@ def main():
     if not args.no_extra:
         out["seed_spread"] = seed_spread(gl, torch, n, max(20, args.steps // 2), args.warmup, r32["value"])
         out["amr"] = amr_leg(gl, torch, max(10, args.steps // 4))
+        out["paper_amr"] = paper_amr_leg(gl, torch, max(5, args.steps // 20))
         out["offplane"] = offplane_leg(gl, torch, max(10, args.steps // 4), fields, n)
         out["batch"] = batch_leg(gl, torch, max(5, args.steps // 20))
         out["serve"] = serve_leg(gl, torch, nreq=max(200, 10 * args.steps))
