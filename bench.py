@@ -328,10 +328,21 @@ def cpu_baseline(n, fields, budget_s=25.0, with_amr=True):
     oracle.direct(lay_rect, s.ravel(), dx.ravel(), dy.ravel(), cent[tg1], threads=1)
     el1 = time.perf_counter() - t1
     amr = cpu_baseline_amr(threads, budget_s / 3) if with_amr else None
+    # the 64^2 Kuzmin disk (M = 1, a = 0.2), every cell against every cell
+    import diskgen
+    X, Y = diskgen.grid_centres(64)
+    ks, kdx, kdy = diskgen.kuzmin(X, Y, 1.0, 0.2)
+    t64 = time.perf_counter()
+    oracle.uniform(ks, kdx, kdy, -1.0, -1.0, 2.0 / 64, threads=threads)
+    el64 = time.perf_counter() - t64
     return {"value": k / el, "unit": "forces/s", "cores": threads, "kind": "oracle",
             "sample": "%d seeded target cells of the %dx%d disk, each summed over all %d source "
                       "cells with the exact kernels (direct method), %.1f s" % (k, n, n, n * n, el),
             "value_1core": 4 / el1, "sample_1core": "4 target cells on one thread, %.1f s" % el1,
+            "kuzmin64_full": {"value": 64 * 64 / el64, "unit": "forces/s",
+                              "sample": "all 4096 cells of the 64x64 Kuzmin disk: the uniform-grid "
+                                        "oracle (closed form per cell offset, then the O(N^4) "
+                                        "compensated sum), %.3f s" % el64},
             **({"amr": amr} if amr else {})}
 
 
@@ -465,9 +476,12 @@ def main():
     col_ms = r32["stages_ms"]["col"]
     achieved = col_bytes(n, 4) / (col_ms * 1e-3) / 1e9
     kname = "grav::k_col<float, %d, %d, 3, 1, 2>" % (2 * n, r32["variants"][1])
+    traffic = stored_traffic(kname, n)
     roof = {"bound": "hbm", "kernel": kname + " (fused column transform, FP32)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, n),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            # counter-measured bytes over the same measured launch time
+            "traffic_gbs": None if traffic is None else traffic / (col_ms * 1e-3) / 1e9,
             "bytes_per_launch": col_bytes(n, 4), "launch_ms": col_ms,
             "copy_gbs": copy_gbs(torch)}
     out = {
