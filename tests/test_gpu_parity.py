@@ -604,3 +604,45 @@ def test_server_rejects_oversized_request(gl):
         srv.submit(p, t, t, t, torch.empty_like(t), torch.empty_like(t))
     assert e.value.status == gl.ENOMEM
     srv.close()
+
+
+def test_solve_replays_from_a_hip_graph(gl):
+    """A solve launches kernels only (no allocation, memset or host wait), so
+    a caller can capture it in a HIP graph: every replay, with eager work and
+    synchronisations between replays, equals the eager result bit for bit."""
+    n = 256
+    s, dx, dy, h = diskgen.noisy_spiral(n, 3)
+    lay, a_s, a_dx, a_dy = diskgen.amr_config(2, n0=64, nlevels=3, thresh=0.1, a=0.05)
+    cases = []
+    for plan, vals in ((gl.Plan(n, gl.F32, h0=h), (s, dx, dy)),
+                       (gl.Plan(lay.n0, gl.F64, nlevels=lay.nlevels, patches=lay.patches),
+                        (a_s, a_dx, a_dy))):
+        dt = plan.torch_dtype
+        t = [torch.from_numpy(np.ascontiguousarray(v).ravel()).to("cuda", dt) for v in vals]
+        out = (torch.empty(plan.n_cells, dtype=dt, device="cuda"),
+               torch.empty(plan.n_cells, dtype=dt, device="cuda"))
+        cases.append((plan, t, out, plan.workspace()))
+    st = torch.cuda.Stream()
+    refs = []
+    with torch.cuda.stream(st):
+        for plan, t, out, ws in cases:
+            plan.solve(*t, fx=out[0], fy=out[1], workspace=ws, stream=st)
+    torch.cuda.synchronize()
+    refs = [(o[0].clone(), o[1].clone()) for _, _, o, _ in cases]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        for plan, t, out, ws in cases:
+            plan.solve(*t, fx=out[0], fy=out[1], workspace=ws, stream=st)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for _, _, out, _ in cases:
+            out[0].fill_(float(rep + 1))
+            out[1].fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, out, _), ref in zip(cases, refs):
+            assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), rep
+        # eager work between replays
+        cases[0][0].solve(*cases[0][1], fx=cases[0][2][0], fy=cases[0][2][1], workspace=cases[0][3])
+        torch.cuda.synchronize()
