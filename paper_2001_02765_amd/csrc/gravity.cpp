@@ -216,6 +216,9 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
     ta.family = family;
     ta.zc = zc;
     gauss_legendre(10, ta.glx, ta.glw);
+    gauss_legendre(8, ta.glx8, ta.glw8);
+    gauss_legendre(6, ta.glx6, ta.glw6);
+    gauss_legendre(4, ta.glx4, ta.glw4);
     hipStream_t s = nullptr;
     for (int kind = 0; kind < nkinds; ++kind) {
         ta.kind = kind;

@@ -84,7 +84,8 @@ struct TableArgs {
     int family;   // 0: cell-centre targets, 1: lattice-corner targets
     int kind;     // 0..8: x0, xx, xy, y0, yx, yy, z0, zx, zy (z kinds need zc != 0)
     double zc;    // height of the target plane above the disk, in cells (0: midplane)
-    double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]
+    double glx[10], glw[10];  // Gauss-Legendre nodes and weights on [-1, 1]: 10 points
+    double glx8[8], glw8[8], glx6[6], glw6[6], glx4[4], glw4[4];  // 8, 6 and 4 points
 };
 
 // Kernel variants of the three solve kernels (see kernels_impl.hpp): bit 1

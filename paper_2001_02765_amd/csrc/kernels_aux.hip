@@ -96,21 +96,26 @@ __device__ double closed_kernel_z(int kind, double uc, double vc, double zc) {
     }
 }
 
-// The same integral by a 10 x 10 Gauss-Legendre rule, used for cells at
-// least 3.5 cells from the target: there the integrand is analytic in a
-// Bernstein ellipse of parameter >= 15 about the cell, so the rule's error
-// is below 1e-23 relative, while the closed form's double difference would
-// cancel ~2 log10(distance) digits.
-__device__ double quad_kernel(int kind, double uc, double vc, const TableArgs &a) {
+// The same integral by an N x N Gauss-Legendre rule, used for cells at
+// least 3.5 cells from the target, where the closed form's double difference
+// would cancel ~2 log10(distance) digits.  At distance D (cells, from the
+// cell's nearest edge) the integrand is analytic in a Bernstein ellipse of
+// parameter rho ~ 4 D about the cell, and the rule's relative error is about
+// rho^(-2N): the order falls with distance, 10 points below 8 cells, 8 below
+// 24, 6 below 128 and 4 beyond, each below 1e-22 relative (1e-19 for the
+// first-moment kinds, whose integral is ~1/D smaller than their integrand).
+template <int N>
+__device__ double quad_kernel(int kind, double uc, double vc, double zc, const double *gx,
+                              const double *gw) {
     double sum = 0.0;
-    for (int i = 0; i < 10; ++i) {
-        const double du = 0.5 * a.glx[i];
+    for (int i = 0; i < N; ++i) {
+        const double du = 0.5 * gx[i];
         const double u = uc + du;
         double si = 0.0;
-        for (int jj = 0; jj < 10; ++jj) {
-            const double dv = 0.5 * a.glx[jj];
+        for (int jj = 0; jj < N; ++jj) {
+            const double dv = 0.5 * gx[jj];
             const double v = vc + dv;
-            const double r2 = u * u + v * v + a.zc * a.zc;
+            const double r2 = u * u + v * v + zc * zc;
             const double ir = 1.0 / sqrt(r2);
             const double ir3 = ir * ir * ir;
             double f;
@@ -121,13 +126,13 @@ __device__ double quad_kernel(int kind, double uc, double vc, const TableArgs &a
                 case 3: f = v; break;
                 case 4: f = du * v; break;
                 case 5: f = dv * v; break;
-                case 6: f = -a.zc; break;
-                case 7: f = -a.zc * du; break;
-                default: f = -a.zc * dv; break;
+                case 6: f = -zc; break;
+                case 7: f = -zc * du; break;
+                default: f = -zc * dv; break;
             }
-            si += a.glw[jj] * f * ir3;
+            si += gw[jj] * f * ir3;
         }
-        sum += a.glw[i] * si;
+        sum += gw[i] * si;
     }
     return 0.25 * sum;
 }
@@ -161,8 +166,15 @@ __global__ void __launch_bounds__(256) k_ktable(TableArgs a) {
             const double off = a.family == 0 ? 0.0 : 0.5;
             const double uc = dx + off, vc = dy + off;
             const double distx = fmax(fabs(uc) - 0.5, 0.0), disty = fmax(fabs(vc) - 0.5, 0.0);
-            if (fmax(distx, disty) >= 3.5) {
-                val = quad_kernel(a.kind, uc, vc, a);
+            const double dist = fmax(distx, disty);
+            if (dist >= 128.0) {
+                val = quad_kernel<4>(a.kind, uc, vc, a.zc, a.glx4, a.glw4);
+            } else if (dist >= 24.0) {
+                val = quad_kernel<6>(a.kind, uc, vc, a.zc, a.glx6, a.glw6);
+            } else if (dist >= 8.0) {
+                val = quad_kernel<8>(a.kind, uc, vc, a.zc, a.glx8, a.glw8);
+            } else if (dist >= 3.5) {
+                val = quad_kernel<10>(a.kind, uc, vc, a.zc, a.glx, a.glw);
             } else if (a.zc != 0.0) {
                 val = closed_kernel_z(a.kind, uc, vc, a.zc);
             } else {
