@@ -68,3 +68,28 @@ def test_band_layout_patches_are_row_runs():
     lay = diskgen.band_layout(64, 2, [(0.0, 0.0)], 0.5, [0.04])
     assert all(p.ny == 2 and p.level == 1 for p in lay.patches)
     assert lay.validate()
+
+
+def test_request_pool_layouts_are_valid_and_in_range():
+    """The served-stream workload: every layout is properly nested, its
+    finest lattice fits the 8192-point transform limit, and its patch count
+    lies in 4..256 when refined."""
+    for lay, prof in diskgen.request_pool(0, count=16):
+        assert lay.validate()
+        assert lay.n0 in (128, 256, 512, 1024, 2048)
+        assert lay.n_finest <= 4096
+        if lay.nlevels > 1:
+            assert 1 <= len(lay.patches) <= 256
+        s, dx, dy = lay.sample(prof)
+        assert np.all(np.isfinite(s)) and np.all(s >= 0)
+        assert s.size == lay.total()
+
+
+def test_batch_disks_shapes_and_seeding():
+    a = diskgen.batch_disks(0)
+    b = diskgen.batch_disks(0)
+    assert len(a) == 64
+    for (n, s, dx, dy), (n2, s2, _, _) in zip(a, b):
+        assert n in (64, 128, 256, 512, 1024) and n == n2
+        assert s.shape == (n, n) and dx.shape == (n, n) and dy.shape == (n, n)
+        assert np.array_equal(s, s2)
