@@ -267,6 +267,21 @@ def test_amr_large_lattices_sampled(gl, prec, n0, levels):
     assert _amr_parity(gl, lay, s, dx, dy, prec, targets=sel) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_amr_six_levels(gl, prec):
+    """Deep nesting: a 32^2 base refined five times along a circle (six
+    levels, leaves up to 32 finest cells wide, finest lattice 1024^2), with a
+    random linear density per leaf: every leaf against the leaf direct sum."""
+    lay = diskgen.band_layout(32, 6, [(0.1, 0.05)], 0.3, [0.08 / 2 ** l for l in range(6)])
+    assert lay.validate() and max(p.level for p in lay.patches) == 5
+    rng = np.random.default_rng(23)
+    n = lay.total()
+    s, dx, dy = rng.random(n) + 0.2, rng.standard_normal(n), rng.standard_normal(n)
+    m = lay.leaf_mask()
+    s, dx, dy = np.where(m, s, 0), np.where(m, dx, 0), np.where(m, dy, 0)
+    assert _amr_parity(gl, lay, s, dx, dy, prec) < TOL[prec]
+
+
 def test_ilr_d2_accuracy_and_order(gl):
     """AMR(2, D2) under ILR (Section 3, Table 3): against the analytic force
     the errors fall at second order in L1 and L2 from N_k = 128 to 256, and
