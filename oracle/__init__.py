@@ -43,6 +43,8 @@ def _load():
                                         ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
         lib.oracle_direct_z.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_nsum.argtypes = [ctypes.c_int64, dp]
+        lib.oracle_nsum.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -59,6 +61,13 @@ def _f64(a):
 
 def max_threads():
     return _load().oracle_max_threads()
+
+
+def nsum(x):
+    """Neumaier-compensated sum of a 1-D array in its order: the summation
+    every force sum of the oracle uses."""
+    x = _f64(x).ravel()
+    return float(_load().oracle_nsum(x.size, _dp(x)))
 
 
 def cell_kernels(xt, yt, xl, xr, yd, yu):

@@ -137,6 +137,16 @@ static inline void nadd(nsum *a, double x)
 }
 static inline double nval(const nsum *a) { return a->s + a->c; }
 
+/* The compensated sum of n doubles in the given order, through the same
+ * nadd / nval that every force sum below uses (exported so that the
+ * summation itself can be checked against an exactly rounded sum). */
+double oracle_nsum(int64_t n, const double *x)
+{
+    nsum a = {0, 0};
+    for (int64_t i = 0; i < n; ++i) nadd(&a, x[i]);
+    return nval(&a);
+}
+
 static int pick_threads(int nthreads)
 {
 #ifdef _OPENMP
