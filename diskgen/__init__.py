@@ -449,6 +449,60 @@ def limit_layout(lay, max_patches, rng):
     return Layout(lay.n0, max(used, 1) if kept else 1, kept, lay.x0, lay.y0, lay.h0)
 
 
+def limit_layout_all_levels(lay, max_patches, rng):
+    """Keep at most max_patches patches (at least one per level), preserving
+    nesting and every level of ``lay``: one chain of patches from level 1 to
+    the deepest level is kept first, then the remaining room is filled level
+    by level with random patches nested in those already kept."""
+    if not lay.patches:
+        return lay
+    deepest = max(p.level for p in lay.patches)
+
+    def inside(c, par):
+        return any(q.i0 <= c.i0 // 2 and c.i0 // 2 + c.nx // 2 <= q.i0 + q.nx and
+                   q.j0 <= c.j0 // 2 and c.j0 // 2 + c.ny // 2 <= q.j0 + q.ny for q in par)
+    chain = [next(p for p in lay.patches if p.level == deepest)]
+    for lvl in range(deepest - 1, 0, -1):
+        chain.append(next(p for p in lay.patches if p.level == lvl and inside(chain[-1], [p])))
+    kept = list(reversed(chain))
+    room = max(max_patches, deepest) - len(kept)
+    for lvl in range(1, deepest + 1):
+        par = [p for p in kept if p.level == lvl - 1]
+        cand = [c for c in lay.patches if c.level == lvl and c not in kept and
+                (lvl == 1 or inside(c, par))]
+        take = min(room, len(cand), int(rng.integers(0, room + 1)) if lvl < deepest else room)
+        if take > 0:
+            idx = sorted(rng.choice(len(cand), take, replace=False))
+            kept.extend(cand[i] for i in idx)
+            room -= take
+    kept.sort(key=lambda p: p.level)
+    return Layout(lay.n0, deepest + 1, kept, lay.x0, lay.y0, lay.h0)
+
+
+def request_pool_full(seed, bases=(128, 256, 512, 1024, 2048), levels=(1, 2, 3, 4)):
+    """The served-stream mix over every base size and level count: one layout
+    per (base, levels) pair, 32x32 child patches flagged on a Kuzmin (scale a
+    ~ U[0.02, 0.2]) plus clumps profile, capped at 4..256 patches (log-
+    uniform) with every level kept.  Returns a list of (layout, profile)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n0 in bases:
+        for lv in levels:
+            a = float(rng.uniform(0.02, 0.2))
+            prof = kuzmin_clumps_profile(int(rng.integers(1 << 30)), a)
+            if lv == 1:
+                out.append((Layout(n0, 1, []), prof))
+                continue
+            thresh = 0.05
+            full = flag_layout(prof, n0, lv, 16, thresh)
+            while max((p.level for p in full.patches), default=0) < lv - 1 and thresh > 1e-4:
+                thresh *= 0.5
+                full = flag_layout(prof, n0, lv, 16, thresh)
+            cap = int(np.exp(rng.uniform(np.log(4), np.log(256))))
+            out.append((limit_layout_all_levels(full, cap, rng), prof))
+    return out
+
+
 def request_pool(seed, count=12, bases=(128, 256, 512, 1024, 2048), max_finest=4096):
     """Distinct AMR request layouts for a served stream: base n0 from `bases`,
     1-4 levels with n0 * 2^(levels-1) <= max_finest, 32x32 child patches
