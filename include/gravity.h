@@ -154,6 +154,27 @@ gravity_status_t gravity_solve_xyz(gravity_plan_t plan, const void *sigma, const
                                    const void *dsy, void *fx, void *fy, void *fz,
                                    void *workspace, void *stream);
 
+/*
+ * Allocation-free solve, for callers that cannot allocate device memory or
+ * hand over a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same inputs, outputs and results as
+ * gravity_solve (bit-identical), but the workspace is a static device array
+ * of GRAVITY_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device
+ * (taken at the first such call on a device and held until the process
+ * ends).  The call allocates nothing.  Every allocation-free solve on one
+ * device shares that array: calls whose work overlaps on the device (other
+ * streams, other threads) race and must be serialised by the caller; solves
+ * queued on one stream are ordered and safe.  No part of the array needs
+ * clearing: each stage writes every workspace element that a later stage
+ * reads.
+ * Errors: as gravity_solve; EUNSUPPORTED if the plan's workspace
+ * (gravity_plan_workspace_bytes) exceeds GRAVITY_NOALLOC_SCRATCH_BYTES
+ * (e.g. FP32 uniform grids up to 1024^2 fit, FP64 up to 512^2).
+ */
+#define GRAVITY_NOALLOC_SCRATCH_BYTES (64u << 20)
+gravity_status_t gravity_solve_noalloc(gravity_plan_t plan, const void *sigma, const void *dsx,
+                                       const void *dsy, void *fx, void *fy, void *stream);
+
 /* Workspace bytes for gravity_solve_batch over these n plans. */
 gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *plans,
                                                size_t *bytes);

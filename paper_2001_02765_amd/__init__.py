@@ -23,11 +23,12 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = range(6)
 F32, F64 = 0, 1
 SLOPES_NONE, SLOPES_GIVEN = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20  # GRAVITY_NOALLOC_SCRATCH_BYTES
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "EBUSY"}
 
 # exported symbols of include/gravity.h
 SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
-           "gravity_solve", "gravity_solve_xyz", "gravity_batch_workspace_bytes", "gravity_solve_batch",
+           "gravity_solve", "gravity_solve_noalloc", "gravity_solve_xyz", "gravity_batch_workspace_bytes", "gravity_solve_batch",
            "gravity_solve_batch_xyz", "gravity_solve_profiled", "gravity_stage_name",
            "gravity_server_create", "gravity_server_submit", "gravity_server_submit_xyz",
            "gravity_server_poll", "gravity_server_wait",
@@ -65,6 +66,8 @@ _lib.gravity_plan_get_info.argtypes = [_vp, ctypes.POINTER(InfoT)]
 _lib.gravity_plan_get_info.restype = ctypes.c_int
 _lib.gravity_solve.argtypes = [_vp] * 8
 _lib.gravity_solve.restype = ctypes.c_int
+_lib.gravity_solve_noalloc.argtypes = [_vp] * 7
+_lib.gravity_solve_noalloc.restype = ctypes.c_int
 _lib.gravity_solve_xyz.argtypes = [_vp] * 9
 _lib.gravity_solve_xyz.restype = ctypes.c_int
 _lib.gravity_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
@@ -258,6 +261,24 @@ class Plan:
                                   _ptr(workspace), _stream_handle(stream)))
         return fx, fy
 
+
+    def solve_noalloc(self, sigma, dsx=None, dsy=None, fx=None, fy=None, stream=None):
+        """As ``solve``, through gravity_solve_noalloc: the library's static
+        per-device scratch array serves as workspace (nothing is allocated;
+        NOALLOC_SCRATCH_BYTES bounds the plan's workspace).  Allocation-free
+        solves whose work overlaps on one device race on that array."""
+        import torch
+        dt = self.torch_dtype
+        self._check_inputs(sigma, dsx, dsy)
+        if fx is None:
+            fx = torch.empty(self.n_cells, dtype=dt, device=sigma.device)
+        if fy is None:
+            fy = torch.empty(self.n_cells, dtype=dt, device=sigma.device)
+        for name, o in (("fx", fx), ("fy", fy)):
+            _check_cells(o, dt, self.n_cells, name)
+        _check(_lib.gravity_solve_noalloc(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx),
+                                          _ptr(fy), _stream_handle(stream)))
+        return fx, fy
 
     def solve_xyz(self, sigma, dsx=None, dsy=None, fx=None, fy=None, fz=None, workspace=None,
                   stream=None):

@@ -835,6 +835,58 @@ gravity_status_t gravity_solve_xyz(gravity_plan_t p, const void *sigma, const vo
     });
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free solves: the workspace is a static device array
+// ---------------------------------------------------------------------------
+// Every device the library runs on holds its own copy of this array from the
+// first allocation-free solve on that device until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: only the
+// address hipGetSymbolAddress returns for the current device is passed to
+// kernels.
+static __device__ __align__(256) unsigned char scratch[GRAVITY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device: device address of `scratch`
+
+void *scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr || ((uintptr_t)ptr & 255)) fail(GRAVITY_EDEVICE, "scratch array has no aligned device address");
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+extern "C" {
+
+gravity_status_t gravity_solve_noalloc(gravity_plan_t p, const void *sigma, const void *dsx,
+                                       const void *dsy, void *fx, void *fy, void *stream) {
+    return guarded([&] {
+        if (!p) fail(GRAVITY_EINVAL, "NULL plan");
+        if (p->ncomp == 3) fail(GRAVITY_EINVAL, "off-plane plan: use gravity_solve_xyz");
+        if (p->ws_bytes > (size_t)GRAVITY_NOALLOC_SCRATCH_BYTES)
+            fail(GRAVITY_EUNSUPPORTED, "plan needs " + std::to_string(p->ws_bytes) +
+                                           " workspace bytes; the allocation-free solve has " +
+                                           std::to_string((size_t)GRAVITY_NOALLOC_SCRATCH_BYTES));
+        int dev = -1;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        if (dev != p->device) fail(GRAVITY_EINVAL, "plan was created on another device");
+        char *ws = (char *)scratch_address(dev);
+        check_solve_args(p, sigma, dsx, dsy, fx, fy, ws);
+        Item it{p, sigma, dsx, dsy, fx, fy, ws};
+        run_items(&it, 1, (hipStream_t)stream);
+    });
+}
+
 gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *plans, size_t *bytes) {
     return guarded([&] {
         if (n < 0 || (n > 0 && !plans) || !bytes) fail(GRAVITY_EINVAL, "bad batch arguments");
