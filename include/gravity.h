@@ -68,6 +68,34 @@ typedef enum { GRAVITY_F32 = 0, GRAVITY_F64 = 1 } gravity_prec_t;
  * piecewise-constant density, dsx = dsy = 0 (first order). */
 typedef enum { GRAVITY_SLOPES_NONE = 0, GRAVITY_SLOPES_GIVEN = 1 } gravity_slopes_t;
 
+/*
+ * How an AMR layout (nlevels > 1) is solved.
+ *
+ * GRAVITY_AMR_EXACT: the leaf-by-leaf sum of Section 2, to rounding.  Every
+ * leaf's linear density is injected onto the finest lattice (exact by the
+ * additivity of the zone integrals) and convolved with the cell-centre and
+ * lattice-corner kernel families; cost follows the finest lattice
+ * (n0 * 2^(nlevels-1) <= 4096 cells per side).
+ *
+ * GRAVITY_AMR_NESTED: an approximation whose cost follows the refined area
+ * (finest lattices beyond 4096 cells per side; nlevels <= 6, midplane only).
+ * Covered cells get the linear density of least-squares distance to their
+ * children (mass and first moments kept); the base grid is solved exactly
+ * with that restricted data; every refined level l is tiled by 64 x 64 boxes
+ * of level-l cells, and at the level-l cells of each box
+ *   F^l = F_fine + interp(F^{l-1} - F_coarse),
+ * where F_fine and F_coarse are exact zero-padded FFT solves of the
+ * level-l and level-(l-1) truncated composites on the box grown by 32
+ * level-l cells on every side (128^2 and 64^2 cell regions), and interp
+ * carries the parent-level difference (the field of everything outside the
+ * region) to the child centres (biquadratic on the 3 x 3 parent cells where
+ * they exist, else bilinear, planar or linear).  The level fields are summed
+ * in FP64 and every leaf takes F^l of its own level.  Its deviation from the
+ * exact leaf sum is of the order of 1e-5 relative (second order in the
+ * parent spacing, largest along box edges).
+ */
+typedef enum { GRAVITY_AMR_EXACT = 0, GRAVITY_AMR_NESTED = 1 } gravity_amr_method_t;
+
 /* A rectangle of nx x ny cells at refinement level `level` (1 .. nlevels-1;
  * the base grid is level 0; refinement ratio 2), lower-left cell (i0, j0) in
  * that level's global cell index.  i0, j0, nx, ny must be even, patches of
@@ -89,11 +117,13 @@ typedef struct {
     double z;                       /* height of the target plane above the disk
                                        (domain units); 0 = midplane (Fx, Fy),
                                        otherwise (Fx, Fy, Fz) at that height */
+    int32_t amr_method;             /* gravity_amr_method_t (AMR layouts only) */
 } gravity_desc_t;
 
 typedef struct {
     int32_t n_finest;    /* finest lattice cells per side, n0 * 2^(nlevels-1) */
-    int32_t fft_size;    /* zero-padded FFT size per side, 2 * n_finest */
+    int32_t fft_size;    /* largest zero-padded FFT size per side: 2 * n_finest
+                            (GRAVITY_AMR_NESTED: 2 * n0, the base solve) */
     int64_t n_cells;     /* composite-packed array length (all cells) */
     int64_t n_leaves;    /* leaf zones (forces computed) */
     size_t workspace_bytes;
@@ -109,7 +139,8 @@ typedef struct {
  * K^{x,y} and the y family; with desc->z != 0 those at height z and the
  * vertical family K^{z,0}, K^{z,x}, K^{z,y}) at every source offset, built
  * in double precision on the device and transformed with a double precision
- * FFT.  Sizes: 16 <= n_finest <= 4096, powers of two.
+ * FFT.  Sizes: 16 <= n_finest <= 4096, powers of two (GRAVITY_AMR_NESTED:
+ * 16 <= n0 <= 4096 and nlevels <= 6, any finest lattice up to 2^30 cells).
  * Kernel variants: unless GRAVITY_AUTOTUNE=0, the first plan of each size,
  * precision and layout kind times every variant of its three FFT kernels
  * and keeps the fastest (GRAVITY_TUNE_FILE persists the choices,
@@ -219,7 +250,8 @@ gravity_status_t gravity_solve_profiled(gravity_plan_t plan, const void *sigma, 
                                         int32_t *nstages);
 
 /* Name of stage `stage` of this plan's pipeline ("" if out of range):
- * uniform plans "row_fwd", "col", "row_inv"; AMR plans add "gather". */
+ * uniform plans "row_fwd", "col", "row_inv"; AMR plans add "gather".
+ * (Plans of GRAVITY_AMR_NESTED are not profiled: EUNSUPPORTED.) */
 const char *gravity_stage_name(gravity_plan_t plan, int32_t stage);
 
 /*
@@ -232,10 +264,19 @@ const char *gravity_stage_name(gravity_plan_t plan, int32_t stage);
  * smaller later ones may pass it), groups admitted requests that can share
  * kernel launches (same size, precision, layout kind) into batches of up to
  * `max_batch`, and queues each batch on the least-loaded stream, so work of
- * different requests overlaps on the device.  Completion is detected by a
- * host callback on the stream; a request's latency runs from submit to that
- * callback (host monotonic clock).  A request's result is bit-identical to a
- * gravity_solve of the same plan and inputs, alone or in any mix.
+ * different requests overlaps on the device.  Ordering with the caller: at
+ * submit an event is recorded on the caller's `stream`, and the server's
+ * stream waits for it before the request's kernels, so inputs written by
+ * work queued earlier on that stream are read only once it is done.  The
+ * dispatcher detects completion by polling an event recorded after each
+ * batch (about every 20 microseconds while work is in flight); a request's
+ * latency runs from submit to that detection (host monotonic clock).  A
+ * request's result is bit-identical to a gravity_solve of the same plan and
+ * inputs, alone or in any mix.  The budget covers request workspaces only:
+ * the plans' resident spectra and maps, and the caller's arrays, are
+ * outside it.  A batch whose launch fails is waited for on its stream before
+ * its arena range is released, and every one of its requests completes with
+ * the error status.
  * Plans and their resident spectra must outlive the requests that use them;
  * inputs and outputs stay caller-owned and must stay valid until completion.
  * Errors: EINVAL (bad arguments), ENOMEM (arena allocation; or, on submit, a
@@ -252,13 +293,17 @@ typedef struct {
 
 gravity_status_t gravity_server_create(size_t hbm_budget_bytes, int32_t nstreams, int32_t max_batch,
                                        gravity_server_t *out);
+/* Queue a solve (arrays as in gravity_solve); `stream`: the caller's stream
+ * that produced the inputs (hipStream_t, NULL = null stream).  Returns a
+ * ticket at once. */
 gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t plan, const void *sigma,
                                        const void *dsx, const void *dsy, void *fx, void *fy,
-                                       int64_t *ticket);
+                                       void *stream, int64_t *ticket);
 /* As gravity_server_submit, with the third output fz of an off-plane plan. */
 gravity_status_t gravity_server_submit_xyz(gravity_server_t srv, gravity_plan_t plan,
                                            const void *sigma, const void *dsx, const void *dsy,
-                                           void *fx, void *fy, void *fz, int64_t *ticket);
+                                           void *fx, void *fy, void *fz, void *stream,
+                                           int64_t *ticket);
 /* *done = 1 once the ticket's solve has completed on the device. */
 gravity_status_t gravity_server_poll(gravity_server_t srv, int64_t ticket, int32_t *done);
 /* Block until the ticket completes; *latency_ms (optional) gets its latency. */

@@ -23,6 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = range(6)
 F32, F64 = 0, 1
 SLOPES_NONE, SLOPES_GIVEN = 0, 1
+AMR_EXACT, AMR_NESTED = 0, 1
 NOALLOC_SCRATCH_BYTES = 64 << 20  # GRAVITY_NOALLOC_SCRATCH_BYTES
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "EBUSY"}
 
@@ -47,7 +48,7 @@ class DescT(ctypes.Structure):
                 ("y0", ctypes.c_double), ("h0", ctypes.c_double), ("nlevels", ctypes.c_int32),
                 ("npatches", ctypes.c_int32), ("patches", ctypes.POINTER(PatchT)),
                 ("prec", ctypes.c_int), ("slopes", ctypes.c_int), ("G", ctypes.c_double),
-                ("z", ctypes.c_double)]
+                ("z", ctypes.c_double), ("amr_method", ctypes.c_int32)]
 
 
 class InfoT(ctypes.Structure):
@@ -101,9 +102,9 @@ class ServerStatsT(ctypes.Structure):
 
 _lib.gravity_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]
 _lib.gravity_server_create.restype = ctypes.c_int
-_lib.gravity_server_submit.argtypes = [_vp] * 7 + [ctypes.POINTER(ctypes.c_int64)]
+_lib.gravity_server_submit.argtypes = [_vp] * 8 + [ctypes.POINTER(ctypes.c_int64)]
 _lib.gravity_server_submit.restype = ctypes.c_int
-_lib.gravity_server_submit_xyz.argtypes = [_vp] * 8 + [ctypes.POINTER(ctypes.c_int64)]
+_lib.gravity_server_submit_xyz.argtypes = [_vp] * 9 + [ctypes.POINTER(ctypes.c_int64)]
 _lib.gravity_server_submit_xyz.restype = ctypes.c_int
 _lib.gravity_server_poll.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
 _lib.gravity_server_poll.restype = ctypes.c_int
@@ -175,10 +176,12 @@ class Plan:
     is [x0, x0 + n0 h0] x [y0, y0 + n0 h0] (default [-1, 1]^2).  z: height of
     the target plane above the disk (0: midplane, solved with ``solve``;
     otherwise the three components at that height, with ``solve_xyz``).
+    amr: "exact" (the leaf sum to rounding, finest lattice <= 4096^2) or
+    "nested" (the nested-correction approximation, cost ~ refined area).
     """
 
     def __init__(self, n0, prec=F32, slopes=True, G=1.0, x0=-1.0, y0=-1.0, h0=None,
-                 nlevels=1, patches=(), z=0.0):
+                 nlevels=1, patches=(), z=0.0, amr="exact"):
         if h0 is None:
             h0 = 2.0 / n0
         pl = list(patches)
@@ -189,7 +192,8 @@ class Plan:
             self._patch_arr[k] = PatchT(*[int(v) for v in p])
         d = DescT(int(n0), int(n0), float(x0), float(y0), float(h0), int(nlevels), len(pl),
                   ctypes.cast(self._patch_arr, ctypes.POINTER(PatchT)), int(prec),
-                  SLOPES_GIVEN if slopes else SLOPES_NONE, float(G), float(z))
+                  SLOPES_GIVEN if slopes else SLOPES_NONE, float(G), float(z),
+                  {"exact": AMR_EXACT, "nested": AMR_NESTED}[amr])
         h = _vp()
         _check(_lib.gravity_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -206,6 +210,7 @@ class Plan:
         self.variants = tuple(info.variants)
         self.ncomp = info.ncomp
         self.z = float(z)
+        self.amr = amr if nlevels > 1 else "exact"
 
     @property
     def handle(self):
@@ -260,7 +265,6 @@ class Plan:
         _check(_lib.gravity_solve(self._h, _ptr(sigma), _ptr(dsx), _ptr(dsy), _ptr(fx), _ptr(fy),
                                   _ptr(workspace), _stream_handle(stream)))
         return fx, fy
-
 
     def solve_noalloc(self, sigma, dsx=None, dsy=None, fx=None, fy=None, stream=None):
         """As ``solve``, through gravity_solve_noalloc: the library's static
@@ -359,10 +363,12 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, plan, sigma, dsx, dsy, fx, fy, fz=None):
+    def submit(self, plan, sigma, dsx, dsy, fx, fy, fz=None, stream=None):
         """Queue a solve (fz: third output of an off-plane plan); tensors must
         stay alive until it completes (the server keeps references until
-        wait()).  Returns a ticket."""
+        wait()).  The server's work waits for what is already queued on
+        ``stream`` (default: torch's current stream), which wrote the inputs.
+        Returns a ticket."""
         plan._check_inputs(sigma, dsx, dsy)
         for name, o in (("fx", fx), ("fy", fy)):
             _check_cells(o, plan.torch_dtype, plan.n_cells, name)
@@ -370,11 +376,12 @@ class Server:
         tk = ctypes.c_int64()
         if fz is None:
             _check(_lib.gravity_server_submit(self._h, plan.handle, _ptr(sigma), _ptr(dsx), _ptr(dsy),
-                                              _ptr(fx), _ptr(fy), ctypes.byref(tk)))
+                                              _ptr(fx), _ptr(fy), _stream_handle(stream),
+                                              ctypes.byref(tk)))
         else:
             _check(_lib.gravity_server_submit_xyz(self._h, plan.handle, _ptr(sigma), _ptr(dsx),
                                                   _ptr(dsy), _ptr(fx), _ptr(fy), _ptr(fz),
-                                                  ctypes.byref(tk)))
+                                                  _stream_handle(stream), ctypes.byref(tk)))
         self._keep[tk.value] = (plan, sigma, dsx, dsy, fx, fy, fz)
         return tk.value
 

@@ -33,10 +33,26 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False):
+def _stale(src):
+    """True if src's object is missing or older than src or any header."""
+    obj = os.path.join(BUILD, src + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+    if src.endswith(".cpp"):  # only the host runtime includes the C ABI header
+        deps += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE)]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose=False, changed_only=False):
+    """Compile every source (changed_only: only those whose object is older
+    than the source or a header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    todo = [s for s in SOURCES if not changed_only or _stale(s)]
+    with ThreadPoolExecutor(max_workers=max(1, len(todo))) as ex:
+        list(ex.map(lambda s: _compile(s, verbose), todo))
+    objs = [os.path.join(BUILD, s + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp]
     if verbose:
@@ -47,4 +63,4 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, changed_only="--changed" in sys.argv))

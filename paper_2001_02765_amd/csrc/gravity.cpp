@@ -22,6 +22,7 @@
 #include <tuple>
 #include <vector>
 
+#include "arena.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -231,6 +232,7 @@ std::shared_ptr<KernelSet> build_kernel_set(int device, int M, int prec, int fam
         ra.out = (C<double> *)rows.p;
         ra.out_pitch = M;
         ra.out_fstride = 0;
+        ra.nrows = M;
         hip_check(launch_row_fwd<double>(rp, 1, M, 0, false, M, 1, (const C<double> *)tw64->tw.p, s),
                   "kernel table row transform");
         const int imag = imag_kind(kind) ? 1 : 0;
@@ -291,6 +293,25 @@ struct gravity_plan_s {
     int var_rf = 0, var_col = 0, var_ri = 0;
     // workspace layout (byte offsets)
     size_t off_a = 0, off_b = 0, off_o = 0, ws_bytes = 0;
+    // GRAVITY_AMR_NESTED plans: sub-plans, box maps and workspace layout
+    std::shared_ptr<struct NestedPlan> nest;
+};
+
+// Nested-correction plan data (see GRAVITY_AMR_NESTED in gravity.h).
+struct NestedPlan {
+    // uniform sub-plans: the base grid, the fine (kNestFine^2) and coarse
+    // (kNestCoarse^2) region solves; they own twiddles, spectra and variants
+    std::unique_ptr<gravity_plan_s> base, fine, coarse;
+    int nbox = 0;                        // boxes over all refined levels
+    std::vector<int> box0, nboxl;        // per level l (index l): first box, count
+    std::vector<int64_t> r_off, r_cnt;   // per level l: restriction entries l -> l-1
+    DevBuf fown, cown;                   // region owner maps [box][R][R]
+    DevBuf rent;                         // restriction entries, 5 int32 each
+    DevBuf leaf;                         // uint8 per composite cell
+    // workspace byte offsets
+    int64_t rstride = 0;  // elements per restricted composite array (cells + zero cell, padded)
+    size_t off_r = 0, off_acc = 0, off_bws = 0, off_bout = 0;
+    size_t off_fa = 0, off_fb = 0, off_fo = 0, off_ca = 0, off_cb = 0, off_co = 0;
 };
 
 namespace {
@@ -420,6 +441,7 @@ struct Item {
 // Solves that can share every launch: same precision, size, fields, layout
 // kind and kernel variants.
 bool same_group(const gravity_plan_s &a, const gravity_plan_s &b) {
+    if (a.nest || b.nest) return &a == &b;  // nested solves run one by one (run_items)
     return a.prec == b.prec && a.M == b.M && a.nfields == b.nfields && a.amr == b.amr &&
            a.ncomp == b.ncomp &&
            a.var_rf == b.var_rf && a.var_col == b.var_col && a.var_ri == b.var_ri &&
@@ -466,6 +488,7 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
         ra.out = (C<T> *)(it[i].ws + p.off_a);
         ra.out_pitch = nf;
         ra.out_fstride = colsz;
+        ra.nrows = nf;
     }
     mark();
     for (int r = 0; r < srep; ++r)
@@ -485,6 +508,8 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
         ca.out = (C<T> *)(it[i].ws + p.off_b);
         ca.out_pitch = nf;
         ca.out_gstride = colsz;
+        ca.nsub = 1;
+        ca.sub_off = 0;
     }
     mark();
     for (int r = 0; r < srep; ++r)
@@ -499,6 +524,7 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
         ia.in_gstride = colsz;
         ia.out_pitch = nf;
         ia.scale = (T)(p.G / ((double)M * (double)M));
+        ia.nrows = nf;
         if (!p.amr) {
             ia.out[0] = (T *)it[i].fx;
             ia.out[1] = (T *)it[i].fy;
@@ -533,7 +559,128 @@ void run_group(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr, i
     mark();
 }
 
+// One batched pass of region solves (all boxes of all refined levels, one
+// launch per kernel): level l is item l - 1 of each pack, its boxes' rows
+// stacked (the row kernels see nbox_l * R rows, the column kernel one
+// sub-item per box).  Inputs are the restricted composite arrays, injected
+// on load through the boxes' region owner maps.
+template <typename T>
+void run_regions(const gravity_plan_s &p, const gravity_plan_s &sp, int R, int coarse, const int32_t *own,
+                 const T *const *in, char *A, char *B, char *O, hipStream_t s) {
+    const NestedPlan &N = *p.nest;
+    const int M = 2 * R, H = M / 2;
+    const int64_t TR = (int64_t)N.nbox * R;  // stacked rows of all boxes
+    const C<T> *tw = (const C<T> *)sp.tw->tw.p;
+    const C<T> *ph = (const C<T> *)sp.tw->ph.p;
+    Pack<RowFwdArgs<T>> rf{};
+    Pack<ColArgs<T>> cp{};
+    Pack<RowInvArgs<T>> ip{};
+    int n = 0, maxsub = 1;
+    int64_t maxrows = 0;
+    for (int l = 1; l < p.nlevels; ++l) {
+        const int nb = N.nboxl[l];
+        if (nb == 0) continue;
+        const int64_t b0 = N.box0[l];
+        const int m = coarse ? l - 1 : l;  // level of the region lattice
+        const T h = (T)(p.h0 / (double)(1 << m));
+        RowFwdArgs<T> &ra = rf.a[n];
+        for (int f = 0; f < 3; ++f) ra.in[f] = in[f];
+        ra.scale[0] = (T)1;
+        ra.scale[1] = h;
+        ra.scale[2] = h;
+        ra.in_pitch = R;
+        ra.owner = own + b0 * R * R;
+        ra.hf = h;
+        ra.slopes = 1;
+        ra.out = (C<T> *)A + b0 * R;
+        ra.out_pitch = TR;
+        ra.out_fstride = H * TR;
+        ra.nrows = (int64_t)nb * R;
+        ColArgs<T> &ca = cp.a[n];
+        ca.in = ra.out;
+        ca.in_pitch = TR;
+        ca.in_fstride = H * TR;
+        ca.q[0] = ca.q[1] = (const T *)sp.centre->q.p;
+        ca.q_pitch = sp.centre->q_pitch;
+        ca.q_kstride = sp.centre->q_kstride;
+        ca.out = (C<T> *)B + b0 * R;
+        ca.out_pitch = TR;
+        ca.out_gstride = H * TR;
+        ca.nsub = nb;
+        ca.sub_off = R;
+        RowInvArgs<T> &ia = ip.a[n];
+        ia.in = ca.out;
+        ia.in_pitch = TR;
+        ia.in_gstride = H * TR;
+        ia.out[0] = (T *)O + b0 * R * R;
+        ia.out[1] = (T *)O + TR * R + b0 * R * R;
+        ia.out_pitch = R;
+        ia.scale = (T)(p.G / ((double)M * (double)M));
+        ia.nrows = (int64_t)nb * R;
+        maxrows = std::max(maxrows, ra.nrows);
+        maxsub = std::max(maxsub, nb);
+        ++n;
+    }
+    if (n == 0) return;
+    hip_check(launch_row_fwd<T>(rf, n, M, sp.var_rf, true, maxrows, 3, tw, s), "region row transform");
+    hip_check(launch_col<T>(cp, n, M, sp.var_col, 3, 1, 2, tw, ph, s, maxsub), "region column transform");
+    hip_check(launch_row_inv<T>(ip, n, M, sp.var_ri, maxrows, 2, tw, s), "region inverse row transform");
+}
+
+template <typename T> void run_nested(const Item &it, hipStream_t s) {
+    const gravity_plan_s &p = *it.p;
+    const NestedPlan &N = *p.nest;
+    const int64_t nc = p.ncells;
+    char *ws = it.ws;
+    T *rs = (T *)(ws + N.off_r), *rdx = rs + N.rstride, *rdy = rdx + N.rstride;
+    double *accx = (double *)(ws + N.off_acc), *accy = accx + nc;
+    hip_check(launch_nest_copy_in<T>((const T *)it.s, p.nfields == 3 ? (const T *)it.dx : nullptr,
+                                     p.nfields == 3 ? (const T *)it.dy : nullptr, rs, rdx, rdy, nc, s),
+              "nested copy-in");
+    for (int l = p.nlevels - 1; l >= 1; --l) {
+        RestrictArgs<T> ra{rs, rdx, rdy, (const int32_t *)N.rent.p + 5 * N.r_off[l], N.r_cnt[l],
+                           p.h0 / (double)(1 << (l - 1))};
+        hip_check(launch_nest_restrict<T>(ra, s), "nested restriction");
+    }
+    // level 0: the base grid with restricted data, solved exactly
+    const int64_t n0sq = (int64_t)p.n0 * p.n0;
+    T *bfx = (T *)(ws + N.off_bout), *bfy = bfx + n0sq;
+    Item bi{N.base.get(), rs, rdx, rdy, bfx, bfy, ws + N.off_bws};
+    run_group<T>(&bi, 1, s);
+    hip_check(launch_nest_lift<T>(bfx, bfy, accx, accy, n0sq, s), "nested lift");
+    const T *in[3] = {rs, rdx, rdy};
+    run_regions<T>(p, *N.fine, kNestFine, 0, (const int32_t *)N.fown.p, in, ws + N.off_fa, ws + N.off_fb,
+                   ws + N.off_fo, s);
+    run_regions<T>(p, *N.coarse, kNestCoarse, 1, (const int32_t *)N.cown.p, in, ws + N.off_ca,
+                   ws + N.off_cb, ws + N.off_co, s);
+    const int64_t fplane = (int64_t)N.nbox * kNestFine * kNestFine;
+    const int64_t cplane = (int64_t)N.nbox * kNestCoarse * kNestCoarse;
+    const T *ffo = (const T *)(ws + N.off_fo), *cfo = (const T *)(ws + N.off_co);
+    for (int l = 1; l < p.nlevels; ++l) {
+        const int64_t b0 = N.box0[l];
+        CombineArgs<T> ca{(const int32_t *)N.fown.p + b0 * kNestFine * kNestFine,
+                          (const int32_t *)N.cown.p + b0 * kNestCoarse * kNestCoarse,
+                          ffo + b0 * kNestFine * kNestFine,
+                          ffo + fplane + b0 * kNestFine * kNestFine,
+                          cfo + b0 * kNestCoarse * kNestCoarse,
+                          cfo + cplane + b0 * kNestCoarse * kNestCoarse,
+                          accx, accy, (int32_t)nc, N.nboxl[l]};
+        hip_check(launch_nest_combine<T>(ca, s), "nested level combine");
+    }
+    hip_check(launch_nest_finalize<T>(accx, accy, (const uint8_t *)N.leaf.p, (T *)it.fx, (T *)it.fy, nc, s),
+              "nested finalize");
+}
+
 void run_items(const Item *it, int n, hipStream_t s, hipEvent_t *ev = nullptr) {
+    if (it[0].p->nest) {  // never grouped: one at a time
+        for (int i = 0; i < n; ++i) {
+            if (it[i].p->prec)
+                run_nested<double>(it[i], s);
+            else
+                run_nested<float>(it[i], s);
+        }
+        return;
+    }
     if (it[0].p->prec)
         run_group<double>(it, n, s, ev);
     else
@@ -690,6 +837,238 @@ void choose_variants(gravity_plan_s &p) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// nested-correction plans: layout validation and maps without any lattice
+// finer than a box region (the finest lattice may reach 2^30 cells per side)
+// ---------------------------------------------------------------------------
+struct PatchRec {
+    int level, i0, j0, nx, ny;
+    int64_t off;  // composite offset of the patch's first cell
+};
+
+// patches of one level binned by kNestBox x kNestBox cell tiles, for lookups
+struct LevelBins {
+    int64_t n = 0;  // lattice cells per side at this level
+    int64_t nb = 0;
+    std::unordered_map<int64_t, std::vector<int>> bins;
+    void add(const PatchRec &q, int id) {
+        for (int64_t by = q.j0 / kNestBox; by <= (q.j0 + q.ny - 1) / kNestBox; ++by)
+            for (int64_t bx = q.i0 / kNestBox; bx <= (q.i0 + q.nx - 1) / kNestBox; ++bx)
+                bins[by * nb + bx].push_back(id);
+    }
+    const std::vector<int> *at(int64_t gi, int64_t gj) const {
+        auto it = bins.find((gj / kNestBox) * nb + gi / kNestBox);
+        return it == bins.end() ? nullptr : &it->second;
+    }
+};
+
+int64_t rect_overlap(int64_t ax0, int64_t ax1, int64_t ay0, int64_t ay1, int64_t bx0, int64_t bx1,
+                     int64_t by0, int64_t by1) {
+    const int64_t w = std::min(ax1, bx1) - std::max(ax0, bx0);
+    const int64_t h = std::min(ay1, by1) - std::max(ay0, by0);
+    return (w > 0 && h > 0) ? w * h : 0;
+}
+
+// owner map of a region of the level-m lattice, R x R cells from (RX, RY):
+// the composite index of the finest cell of level <= m covering each region
+// cell | log2(its size in level-m cells) << 28; `sentinel` outside the domain
+void region_owner(const gravity_plan_s &p, const std::vector<PatchRec> &pr, int m, int64_t RX, int64_t RY,
+                  int R, int32_t sentinel, int32_t *out) {
+    const int64_t nm = (int64_t)p.n0 << m;
+    for (int y = 0; y < R; ++y)
+        for (int x = 0; x < R; ++x) {
+            const int64_t gx = RX + x, gy = RY + y;
+            int32_t v = sentinel;
+            if (gx >= 0 && gy >= 0 && gx < nm && gy < nm)
+                v = (int32_t)((gy >> m) * p.n0 + (gx >> m)) | (m << 28);
+            out[(size_t)y * R + x] = v;
+        }
+    for (int k = 1; k <= m; ++k) {
+        const int sh = m - k;
+        for (const PatchRec &q : pr) {
+            if (q.level != k) continue;
+            const int64_t x0 = std::max<int64_t>(RX, (int64_t)q.i0 << sh);
+            const int64_t x1 = std::min<int64_t>(RX + R, (int64_t)(q.i0 + q.nx) << sh);
+            const int64_t y0 = std::max<int64_t>(RY, (int64_t)q.j0 << sh);
+            const int64_t y1 = std::min<int64_t>(RY + R, (int64_t)(q.j0 + q.ny) << sh);
+            for (int64_t gy = y0; gy < y1; ++gy)
+                for (int64_t gx = x0; gx < x1; ++gx) {
+                    const int64_t c = q.off + ((gy >> sh) - q.j0) * q.nx + ((gx >> sh) - q.i0);
+                    out[(size_t)(gy - RY) * R + (gx - RX)] = (int32_t)c | (sh << 28);
+                }
+        }
+    }
+}
+
+std::unique_ptr<gravity_plan_s> sub_plan(const gravity_plan_s &p, int n, double h0) {
+    gravity_desc_t d{};
+    d.n0x = d.n0y = n;
+    d.x0 = p.x0;
+    d.y0 = p.y0;
+    d.h0 = h0;
+    d.nlevels = 1;
+    d.prec = (gravity_prec_t)p.prec;
+    d.slopes = GRAVITY_SLOPES_GIVEN;
+    d.G = p.G;
+    gravity_plan_t sp = nullptr;
+    const gravity_status_t st = gravity_plan(&d, &sp);
+    if (st != GRAVITY_OK) fail(st, std::string("nested sub-plan: ") + gravity_last_error());
+    return std::unique_ptr<gravity_plan_s>(sp);
+}
+
+void build_nested(gravity_plan_s &p) {
+    const int L = p.nlevels;
+    auto N = std::make_shared<NestedPlan>();
+    // patches, composite offsets, validity
+    std::vector<PatchRec> pr;
+    int64_t off = (int64_t)p.n0 * p.n0;
+    std::vector<LevelBins> lb(L);
+    for (int l = 0; l < L; ++l) {
+        lb[l].n = (int64_t)p.n0 << l;
+        lb[l].nb = (lb[l].n + kNestBox - 1) / kNestBox;
+    }
+    for (auto &q : p.patches) {
+        if (q.level < 1 || q.level >= L) fail(GRAVITY_EINVAL, "patch level out of range");
+        if (q.nx <= 0 || q.ny <= 0) fail(GRAVITY_EINVAL, "empty patch");
+        if ((q.i0 | q.j0 | q.nx | q.ny) & 1) fail(GRAVITY_EINVAL, "patch corners and sizes must be even");
+        const int64_t nl = (int64_t)p.n0 << q.level;
+        if (q.i0 < 0 || q.j0 < 0 || q.i0 + (int64_t)q.nx > nl || q.j0 + (int64_t)q.ny > nl)
+            fail(GRAVITY_EINVAL, "patch outside the domain");
+        pr.push_back(PatchRec{q.level, q.i0, q.j0, q.nx, q.ny, off});
+        off += (int64_t)q.nx * q.ny;
+        if (off >= (1 << 28) - 1) fail(GRAVITY_EUNSUPPORTED, "too many composite cells");
+    }
+    p.ncells = off;
+    for (size_t k = 0; k < pr.size(); ++k) lb[pr[k].level].add(pr[k], (int)k);
+    // no overlap within a level
+    for (int l = 1; l < L; ++l)
+        for (auto &kv : lb[l].bins) {
+            const auto &v = kv.second;
+            for (size_t a = 0; a < v.size(); ++a)
+                for (size_t b = a + 1; b < v.size(); ++b) {
+                    const PatchRec &A = pr[v[a]], &Bq = pr[v[b]];
+                    if (rect_overlap(A.i0, A.i0 + A.nx, A.j0, A.j0 + A.ny, Bq.i0, Bq.i0 + Bq.nx, Bq.j0,
+                                     Bq.j0 + Bq.ny))
+                        fail(GRAVITY_EINVAL, "overlapping patches on one level");
+                }
+        }
+    // composite index of the level-k cell (gi, gj), -1 if level k has none
+    auto lookup = [&](int k, int64_t gi, int64_t gj) -> int64_t {
+        if (k == 0) return gj * p.n0 + gi;
+        const std::vector<int> *v = lb[k].at(gi, gj);
+        if (!v) return -1;
+        for (int id : *v) {
+            const PatchRec &q = pr[id];
+            if (gi >= q.i0 && gi < q.i0 + q.nx && gj >= q.j0 && gj < q.j0 + q.ny)
+                return q.off + (gj - q.j0) * q.nx + (gi - q.i0);
+        }
+        return -1;
+    };
+    // nesting, leaves and the restriction entries (children level l -> l-1)
+    std::vector<uint8_t> leaf((size_t)p.ncells, 1);
+    std::vector<std::vector<int32_t>> ent(L);
+    for (const PatchRec &q : pr) {
+        const int l = q.level;
+        for (int64_t J = q.j0 / 2; J < (q.j0 + q.ny) / 2; ++J)
+            for (int64_t I = q.i0 / 2; I < (q.i0 + q.nx) / 2; ++I) {
+                const int64_t c = lookup(l - 1, I, J);
+                if (c < 0) fail(GRAVITY_EINVAL, "patch not nested inside the level below");
+                leaf[(size_t)c] = 0;
+                const int64_t ci = 2 * I - q.i0, cj = 2 * J - q.j0;
+                auto child = [&](int a, int b) { return (int32_t)(q.off + (cj + b) * q.nx + ci + a); };
+                ent[l].insert(ent[l].end(), {(int32_t)c, child(0, 0), child(1, 0), child(0, 1), child(1, 1)});
+            }
+    }
+    int64_t leaves = 0;
+    for (auto v : leaf) leaves += v;
+    p.nleaves = leaves;
+    N->r_off.assign(L, 0);
+    N->r_cnt.assign(L, 0);
+    std::vector<int32_t> rent;
+    for (int l = 1; l < L; ++l) {
+        N->r_off[l] = (int64_t)rent.size() / 5;
+        N->r_cnt[l] = (int64_t)ent[l].size() / 5;
+        rent.insert(rent.end(), ent[l].begin(), ent[l].end());
+    }
+    // boxes of every refined level, ordered by level then (by, bx)
+    N->box0.assign(L, 0);
+    N->nboxl.assign(L, 0);
+    std::vector<std::pair<int, std::pair<int64_t, int64_t>>> boxes;  // (level, (by, bx))
+    for (int l = 1; l < L; ++l) {
+        std::vector<std::pair<int64_t, int64_t>> bl;
+        for (const PatchRec &q : pr) {
+            if (q.level != l) continue;
+            for (int64_t by = q.j0 / kNestBox; by <= (q.j0 + q.ny - 1) / kNestBox; ++by)
+                for (int64_t bx = q.i0 / kNestBox; bx <= (q.i0 + q.nx - 1) / kNestBox; ++bx)
+                    bl.push_back({by, bx});
+        }
+        std::sort(bl.begin(), bl.end());
+        bl.erase(std::unique(bl.begin(), bl.end()), bl.end());
+        N->box0[l] = (int)boxes.size();
+        N->nboxl[l] = (int)bl.size();
+        if (bl.size() > 65535) fail(GRAVITY_EUNSUPPORTED, "more than 65535 boxes on one level");
+        for (auto &b : bl) boxes.push_back({l, b});
+    }
+    N->nbox = (int)boxes.size();
+    const int32_t sentinel = (int32_t)p.ncells;
+    std::vector<int32_t> fown((size_t)N->nbox * kNestFine * kNestFine);
+    std::vector<int32_t> cown((size_t)N->nbox * kNestCoarse * kNestCoarse);
+    for (int b = 0; b < N->nbox; ++b) {
+        const int l = boxes[b].first;
+        const int64_t X0 = boxes[b].second.second * kNestBox, Y0 = boxes[b].second.first * kNestBox;
+        region_owner(p, pr, l, X0 - kNestExt, Y0 - kNestExt, kNestFine, sentinel,
+                     fown.data() + (size_t)b * kNestFine * kNestFine);
+        region_owner(p, pr, l - 1, X0 / 2 - kNestExt / 2, Y0 / 2 - kNestExt / 2, kNestCoarse, sentinel,
+                     cown.data() + (size_t)b * kNestCoarse * kNestCoarse);
+    }
+    // every index the kernels will follow stays inside its array
+    for (auto *v : {&fown, &cown})
+        for (int32_t o : *v)
+            if ((o & 0x0FFFFFFF) > sentinel || ((o >> 28) & 0xF) > kNestMaxLevels)
+                fail(GRAVITY_EDEVICE, "internal error: nested region map out of range");
+    for (int32_t c : rent)
+        if (c < 0 || c >= sentinel) fail(GRAVITY_EDEVICE, "internal error: restriction entry out of range");
+    // sub-plans (kernel spectra and variants of the three uniform sizes)
+    N->base = sub_plan(p, p.n0, p.h0);
+    N->fine = sub_plan(p, kNestFine, 2.0 / kNestFine);
+    N->coarse = sub_plan(p, kNestCoarse, 2.0 / kNestCoarse);
+    // device maps
+    auto upload = [](DevBuf &d, const void *src, size_t bytes, const char *what) {
+        d.alloc(bytes, what);
+        if (bytes) hip_check(hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice), what);
+    };
+    upload(N->fown, fown.data(), fown.size() * sizeof(int32_t), "nested fine region maps");
+    upload(N->cown, cown.data(), cown.size() * sizeof(int32_t), "nested coarse region maps");
+    upload(N->rent, rent.data(), rent.size() * sizeof(int32_t), "nested restriction entries");
+    upload(N->leaf, leaf.data(), leaf.size(), "nested leaf flags");
+    // workspace layout
+    const size_t esz = p.prec ? sizeof(double) : sizeof(float);
+    const int64_t nc = p.ncells, n0sq = (int64_t)p.n0 * p.n0, nb = N->nbox;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    N->rstride = (nc + 1 + 63) / 64 * 64;  // keeps every array two-element aligned
+    N->off_r = take(3 * esz * (size_t)N->rstride);
+    N->off_acc = take(2 * sizeof(double) * (size_t)nc);
+    N->off_bws = take(N->base->ws_bytes);
+    N->off_bout = take(2 * esz * (size_t)n0sq);
+    const size_t fcols = (size_t)kNestFine * nb * kNestFine, ccols = (size_t)kNestCoarse * nb * kNestCoarse;
+    N->off_fa = take(3 * 2 * esz * fcols);   // M/2 = kNestFine columns of nb * kNestFine rows
+    N->off_fb = take(2 * 2 * esz * fcols);
+    N->off_fo = take(2 * esz * fcols);
+    N->off_ca = take(3 * 2 * esz * ccols);
+    N->off_cb = take(2 * 2 * esz * ccols);
+    N->off_co = take(2 * esz * ccols);
+    p.ws_bytes = o;
+    p.nest = N;
+    p.var_rf = N->base->var_rf;
+    p.var_col = N->base->var_col;
+    p.var_ri = N->base->var_ri;
+}
+
 extern "C" {
 
 gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
@@ -707,9 +1086,18 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
             fail(GRAVITY_EINVAL, "bad slope mode");
         if (d->npatches < 0 || (d->npatches > 0 && !d->patches)) fail(GRAVITY_EINVAL, "bad patch list");
         if (d->nlevels == 1 && d->npatches > 0) fail(GRAVITY_EINVAL, "patches need nlevels > 1");
+        if (d->amr_method != GRAVITY_AMR_EXACT && d->amr_method != GRAVITY_AMR_NESTED)
+            fail(GRAVITY_EINVAL, "bad AMR method");
+        const bool nested = d->amr_method == GRAVITY_AMR_NESTED && d->nlevels > 1;
         const int64_t nf = (int64_t)d->n0x << (d->nlevels - 1);
-        if (nf < 16 || nf > kMaxM / 2)
+        if (nested) {
+            if (d->n0x < 16 || d->n0x > kMaxM / 2)
+                fail(GRAVITY_EUNSUPPORTED, "nested AMR: base grid must have 16..4096 cells per side");
+            if (d->nlevels > kNestMaxLevels) fail(GRAVITY_EUNSUPPORTED, "nested AMR: at most 6 levels");
+            if (d->z != 0.0) fail(GRAVITY_EUNSUPPORTED, "nested AMR: midplane targets only");
+        } else if (nf < 16 || nf > kMaxM / 2) {
             fail(GRAVITY_EUNSUPPORTED, "finest lattice must have 16..4096 cells per side");
+        }
         auto p = std::make_unique<gravity_plan_s>();
         p->prec = d->prec;
         p->slopes = d->slopes;
@@ -722,10 +1110,18 @@ gravity_status_t gravity_plan(const gravity_desc_t *d, gravity_plan_t *out) {
         p->y0 = d->y0;
         p->h0 = d->h0;
         p->patches.assign(d->patches, d->patches + d->npatches);
+        p->nfields = d->slopes == GRAVITY_SLOPES_GIVEN ? 3 : 1;
+        if (nested) {
+            hip_check(hipGetDevice(&p->device), "hipGetDevice");
+            p->nf = (int)std::min<int64_t>(nf, 1 << 30);
+            p->M = 2 * p->n0;
+            build_nested(*p);
+            *out = p.release();
+            return;
+        }
         p->nf = (int)nf;
         p->M = 2 * p->nf;
         p->amr = d->nlevels > 1;
-        p->nfields = d->slopes == GRAVITY_SLOPES_GIVEN ? 3 : 1;
         std::vector<int32_t> owner, gmap;
         if (p->amr) {
             validate_and_build_maps(*p, owner, gmap);
@@ -789,6 +1185,12 @@ gravity_status_t gravity_plan_get_info(gravity_plan_t p, gravity_plan_info_t *in
         if (p->centre) r += p->centre->q.bytes;
         if (p->corner) r += p->corner->q.bytes;
         if (p->tw) r += p->tw->tw.bytes + p->tw->ph.bytes;
+        if (p->nest) {
+            const NestedPlan &N = *p->nest;
+            r += N.fown.bytes + N.cown.bytes + N.rent.bytes + N.leaf.bytes;
+            for (const gravity_plan_s *sp : {N.base.get(), N.fine.get(), N.coarse.get()})
+                r += sp->centre->q.bytes + sp->tw->tw.bytes + sp->tw->ph.bytes;
+        }
         info->resident_bytes = r;
         info->ncomp = p->ncomp;
         info->variants[0] = p->var_rf;
@@ -930,8 +1332,9 @@ static gravity_status_t solve_batch(int32_t n, const gravity_plan_t *plans, cons
         std::vector<Item> grp;
         for (int i = 0; i < n; ++i) {
             if (done[i]) continue;
-            grp.clear();
-            for (int j = i; j < n; ++j) {
+            grp.assign(1, items[i]);
+            done[i] = true;
+            for (int j = i + 1; j < n; ++j) {
                 if (!done[j] && same_group(*items[i].p, *items[j].p)) {
                     grp.push_back(items[j]);
                     done[j] = true;
@@ -963,6 +1366,7 @@ gravity_status_t gravity_solve_profiled(gravity_plan_t p, const void *sigma, con
         check_solve_args(p, sigma, dsx, dsy, fx, fy, workspace);
         if (reps < 1 || !stage_ms || !nstages) fail(GRAVITY_EINVAL, "bad profiling arguments");
         if (p->ncomp == 3) fail(GRAVITY_EUNSUPPORTED, "off-plane plans are solved with gravity_solve_xyz");
+        if (p->nest) fail(GRAVITY_EUNSUPPORTED, "nested AMR plans are not profiled by stage");
         const int ns = n_stages(*p);
         ev.resize(ns + 1);
         for (auto &e : ev) {
@@ -1018,52 +1422,6 @@ const char *gravity_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 namespace {
 
-// first-fit sub-allocator over one device allocation (offsets, 256 B units)
-class Arena {
-  public:
-    explicit Arena(size_t size) : size_(size) {
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = align256(bytes ? bytes : 1);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align256(bytes ? bytes : 1);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-
-  private:
-    size_t size_, used_ = 0;
-    std::map<size_t, size_t> free_;
-};
-
 using Clock = std::chrono::steady_clock;
 
 struct SrvRequest {
@@ -1071,6 +1429,7 @@ struct SrvRequest {
     Item item;  // ws filled at admission
     size_t ws_bytes, off = 0;
     Clock::time_point t_submit;
+    hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
 };
 
 struct SrvTicket {
@@ -1091,10 +1450,10 @@ struct gravity_server_s {
     int device = 0;
     int max_batch = kPack;
     DevBuf arena_mem;
-    std::unique_ptr<Arena> arena;
+    std::unique_ptr<grav::Arena> arena;
     std::vector<hipStream_t> streams;
     std::vector<int> load;
-    std::vector<hipEvent_t> event_pool;
+    std::vector<hipEvent_t> event_pool;  // completion and input-ready events
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<SrvRequest> pending;
@@ -1109,7 +1468,22 @@ struct gravity_server_s {
 
     void loop();
     void complete(SrvBatch &b, gravity_status_t st);
+    hipEvent_t take_event();  // with mu held; nullptr if creation fails
 };
+
+hipEvent_t gravity_server_s::take_event() {
+    if (event_pool.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+}
 
 void gravity_server_s::complete(SrvBatch &b, gravity_status_t st) {
     // called with mu held
@@ -1124,10 +1498,11 @@ void gravity_server_s::complete(SrvBatch &b, gravity_status_t st) {
             leaves += r.item.p->nleaves;
         }
         arena->release(r.off, r.ws_bytes);
+        if (r.ready) event_pool.push_back(r.ready);
         ++completed;
     }
     --load[b.stream];
-    event_pool.push_back(b.ev);
+    if (b.ev) event_pool.push_back(b.ev);
 }
 
 void gravity_server_s::loop() {
@@ -1154,7 +1529,9 @@ void gravity_server_s::loop() {
         for (size_t i = 0; i < admitted.size(); ++i) {
             if (used[i]) continue;
             SrvBatch b;
-            for (size_t j = i; j < admitted.size() && (int)b.reqs.size() < max_batch; ++j) {
+            b.reqs.push_back(admitted[i]);
+            used[i] = true;
+            for (size_t j = i + 1; j < admitted.size() && (int)b.reqs.size() < max_batch; ++j) {
                 if (!used[j] && same_group(*admitted[i].item.p, *admitted[j].item.p)) {
                     b.reqs.push_back(admitted[j]);
                     used[j] = true;
@@ -1162,13 +1539,7 @@ void gravity_server_s::loop() {
             }
             b.stream = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             ++load[b.stream];
-            if (event_pool.empty()) {
-                hipEvent_t e = nullptr;
-                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
-                event_pool.push_back(e);
-            }
-            b.ev = event_pool.back();
-            event_pool.pop_back();
+            b.ev = take_event();
             ready.push_back(std::move(b));
         }
         // launch without holding the lock
@@ -1176,15 +1547,29 @@ void gravity_server_s::loop() {
         std::vector<gravity_status_t> st(ready.size(), GRAVITY_OK);
         for (size_t k = 0; k < ready.size(); ++k) {
             SrvBatch &b = ready[k];
-            std::vector<Item> items;
-            for (auto &r : b.reqs) items.push_back(r.item);
+            hipStream_t sb = streams[b.stream];
+            bool queued = false;  // kernels of this batch may be on the stream
             try {
                 if (!b.ev) fail(GRAVITY_EDEVICE, "hipEventCreate failed");
-                run_items(items.data(), (int)items.size(), streams[b.stream]);
-                hip_check(hipEventRecord(b.ev, streams[b.stream]), "hipEventRecord");
+                std::vector<Item> items;
+                for (auto &r : b.reqs) {
+                    items.push_back(r.item);
+                    // the request's inputs: ready once the caller's stream reached submit
+                    hip_check(hipStreamWaitEvent(sb, r.ready, 0), "hipStreamWaitEvent");
+                }
+                queued = true;
+                run_items(items.data(), (int)items.size(), sb);
+                hip_check(hipEventRecord(b.ev, sb), "hipEventRecord");
             } catch (const Failure &f) {
                 st[k] = f.st;
+            } catch (const std::bad_alloc &) {
+                st[k] = GRAVITY_ENOMEM;
+            } catch (...) {
+                st[k] = GRAVITY_EDEVICE;
             }
+            // a failed batch releases its arena range at once: first let
+            // whatever it queued finish
+            if (st[k] != GRAVITY_OK && queued) (void)hipStreamSynchronize(sb);
         }
         lk.lock();
         for (size_t k = 0; k < ready.size(); ++k) {
@@ -1229,7 +1614,7 @@ gravity_status_t gravity_server_create(size_t budget, int32_t nstreams, int32_t 
         hip_check(hipGetDevice(&srv->device), "hipGetDevice");
         srv->max_batch = std::min<int>(max_batch, kPack);
         srv->arena_mem.alloc(budget, "server arena");
-        srv->arena = std::make_unique<Arena>(budget);
+        srv->arena = std::make_unique<grav::Arena>(budget);
         for (int i = 0; i < nstreams; ++i) {
             hipStream_t s = nullptr;
             hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
@@ -1243,7 +1628,7 @@ gravity_status_t gravity_server_create(size_t budget, int32_t nstreams, int32_t 
 }
 
 static gravity_status_t server_submit(gravity_server_t srv, gravity_plan_t p, const void *sigma, const void *dsx,
-                               const void *dsy, void *fx, void *fy, void *fz, int64_t *ticket) {
+                               const void *dsy, void *fx, void *fy, void *fz, void *stream, int64_t *ticket) {
     return guarded([&] {
         if (!srv || !ticket) fail(GRAVITY_EINVAL, "NULL argument");
         alignas(256) static char aligned_dummy;
@@ -1261,6 +1646,13 @@ static gravity_status_t server_submit(gravity_server_t srv, gravity_plan_t p, co
         {
             std::lock_guard<std::mutex> lk(srv->mu);
             if (srv->stop) fail(GRAVITY_EBUSY, "server is shutting down");
+            r.ready = srv->take_event();
+            if (!r.ready) fail(GRAVITY_EDEVICE, "hipEventCreate failed");
+            const hipError_t e = hipEventRecord(r.ready, (hipStream_t)stream);
+            if (e != hipSuccess) {
+                srv->event_pool.push_back(r.ready);
+                hip_check(e, "hipEventRecord on the caller's stream");
+            }
             r.ticket = srv->next_ticket++;
             srv->tickets[r.ticket] = SrvTicket{};
             srv->pending.push_back(r);
@@ -1272,15 +1664,15 @@ static gravity_status_t server_submit(gravity_server_t srv, gravity_plan_t p, co
 }
 
 gravity_status_t gravity_server_submit(gravity_server_t srv, gravity_plan_t p, const void *sigma,
-                                       const void *dsx, const void *dsy, void *fx, void *fy,
+                                       const void *dsx, const void *dsy, void *fx, void *fy, void *stream,
                                        int64_t *ticket) {
-    return server_submit(srv, p, sigma, dsx, dsy, fx, fy, nullptr, ticket);
+    return server_submit(srv, p, sigma, dsx, dsy, fx, fy, nullptr, stream, ticket);
 }
 
 gravity_status_t gravity_server_submit_xyz(gravity_server_t srv, gravity_plan_t p, const void *sigma,
                                            const void *dsx, const void *dsy, void *fx, void *fy, void *fz,
-                                           int64_t *ticket) {
-    return server_submit(srv, p, sigma, dsx, dsy, fx, fy, fz, ticket);
+                                           void *stream, int64_t *ticket) {
+    return server_submit(srv, p, sigma, dsx, dsy, fx, fy, fz, stream, ticket);
 }
 
 gravity_status_t gravity_server_poll(gravity_server_t srv, int64_t ticket, int32_t *done) {

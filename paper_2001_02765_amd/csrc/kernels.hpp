@@ -32,6 +32,7 @@ template <typename T> struct RowFwdArgs {
     const int32_t *owner;
     T hf;
     int slopes;
+    int64_t nrows;      // rows of this item (items of one launch may differ)
 };
 
 template <typename T> struct ColArgs {
@@ -41,6 +42,10 @@ template <typename T> struct ColArgs {
     int64_t q_pitch, q_kstride;
     C<T> *out;       // B
     int64_t out_pitch, out_gstride;
+    // sub-items (blockIdx.y < nsub): independent column sets of one size
+    // whose input and output columns start sub_off elements further on
+    int nsub;
+    int64_t sub_off;
 };
 
 template <typename T> struct RowInvArgs {
@@ -49,6 +54,7 @@ template <typename T> struct RowInvArgs {
     T *out[6];       // one real plane per output (component x family)
     int64_t out_pitch;
     T scale;
+    int64_t nrows;   // rows of this item (items of one launch may differ)
 };
 
 template <typename T> struct GatherArgs {
@@ -98,17 +104,58 @@ bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam, int ncomp);
 
 // Launchers: n (1..kPack) items of the same size and kind in one launch.
+// nrows / nsub: the largest item's rows / sub-items (the grid is sized for
+// it; the blocks beyond a smaller item's own count exit at once).
 template <typename T>
 hipError_t launch_row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int M, int var, bool pruned,
-                          int nrows, int nfields, const C<T> *tw, hipStream_t s);
+                          int64_t nrows, int nfields, const C<T> *tw, hipStream_t s);
 template <typename T>
 hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfields, int nfam,
-                      int ncomp, const C<T> *tw, const C<T> *ph, hipStream_t s);
+                      int ncomp, const C<T> *tw, const C<T> *ph, hipStream_t s, int nsub = 1);
 template <typename T>
-hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,
+hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int64_t nrows, int nout,
                           const C<T> *tw, hipStream_t s);
 template <typename T>
 hipError_t launch_gather(const Pack<GatherArgs<T>> &a, int n, int64_t maxcells, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// nested-correction AMR (approximate; cost follows the refined area)
+// ---------------------------------------------------------------------------
+// Each refined level l >= 1 is tiled by kNestBox x kNestBox boxes of level-l
+// cells; a box is solved on its region grown by kNestExt cells on every side
+// (fine region: kNestFine^2 level-l cells, coarse region: kNestCoarse^2
+// level-(l-1) cells).
+constexpr int kNestBox = 64, kNestExt = 32;
+constexpr int kNestFine = kNestBox + 2 * kNestExt, kNestCoarse = kNestFine / 2;
+constexpr int kNestMaxLevels = 6;  // region origins stay aligned to every leaf size
+
+// restriction of four children into their parent (per entry: parent and
+// children (x, y) = (0,0), (1,0), (0,1), (1,1), composite indices)
+template <typename T> struct RestrictArgs {
+    T *s, *dx, *dy;          // composite arrays, updated in place
+    const int32_t *ent;      // 5 indices per entry
+    int64_t n;               // entries
+    double h;                // parent cell size
+};
+// combine of one refined level: F^l = F_fine + sum_k w_k (F^{l-1}(p_k) - F_coarse(p_k))
+template <typename T> struct CombineArgs {
+    const int32_t *fown, *cown;  // region owner maps of this level's boxes
+    const T *ffx, *ffy;          // fine-region forces [box][kNestFine^2]
+    const T *cfx, *cfy;          // coarse-region forces [box][kNestCoarse^2]
+    double *accx, *accy;         // per composite cell: F^l of its level (FP64)
+    int32_t sentinel;            // owner index of cells outside the domain
+    int nbox;
+};
+template <typename T>
+hipError_t launch_nest_copy_in(const T *s, const T *dx, const T *dy, T *rs, T *rdx, T *rdy, int64_t n,
+                               hipStream_t st);
+template <typename T> hipError_t launch_nest_restrict(const RestrictArgs<T> &a, hipStream_t st);
+template <typename T>
+hipError_t launch_nest_lift(const T *fx, const T *fy, double *accx, double *accy, int64_t n, hipStream_t st);
+template <typename T> hipError_t launch_nest_combine(const CombineArgs<T> &a, hipStream_t st);
+template <typename T>
+hipError_t launch_nest_finalize(const double *accx, const double *accy, const uint8_t *leaf, T *fx, T *fy,
+                                int64_t n, hipStream_t st);
 
 hipError_t launch_ktable(const TableArgs &a, hipStream_t s);
 // forward FFT of the columns of a table's row spectra (odd x frequencies)

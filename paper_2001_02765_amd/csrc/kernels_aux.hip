@@ -233,6 +233,168 @@ template <typename T> __global__ void __launch_bounds__(256) k_gather(Pack<Gathe
 }
 
 // ---------------------------------------------------------------------------
+// nested-correction AMR
+// ---------------------------------------------------------------------------
+// composite inputs -> working copy (absent slopes read as 0), plus one zero
+// cell at index n that region cells outside the domain point to
+template <typename T>
+__global__ void __launch_bounds__(256) k_nest_copy_in(const T *s, const T *dx, const T *dy, T *rs, T *rdx,
+                                                      T *rdy, int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > n) return;
+    if (c == n) {
+        rs[c] = 0;
+        rdx[c] = 0;
+        rdy[c] = 0;
+        return;
+    }
+    rs[c] = s[c];
+    rdx[c] = dx ? dx[c] : (T)0;
+    rdy[c] = dy ? dy[c] : (T)0;
+}
+
+// The linear density of least-squares distance to four children's linear
+// pieces: mean value, and slopes 3/(4h) (right - left children sum) plus the
+// mean child slope / 4; conserves mass and both first moments (Section 2's
+// zone integrals of a first-order Taylor density).
+template <typename T> __global__ void __launch_bounds__(256) k_nest_restrict(RestrictArgs<T> a) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.n) return;
+    const int32_t *q = a.ent + 5 * e;
+    const int32_t p = q[0], c00 = q[1], c10 = q[2], c01 = q[3], c11 = q[4];
+    const double s00 = a.s[c00], s10 = a.s[c10], s01 = a.s[c01], s11 = a.s[c11];
+    const double k = 3.0 / (4.0 * a.h);
+    const double gx = (double)a.dx[c00] + (double)a.dx[c01] + (double)a.dx[c10] + (double)a.dx[c11];
+    const double gy = (double)a.dy[c00] + (double)a.dy[c01] + (double)a.dy[c10] + (double)a.dy[c11];
+    a.s[p] = (T)((s00 + s10 + s01 + s11) / 4.0);
+    a.dx[p] = (T)(k * ((s10 + s11) - (s00 + s01)) + gx / 16.0);
+    a.dy[p] = (T)(k * ((s01 + s11) - (s00 + s10)) + gy / 16.0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_nest_lift(const T *fx, const T *fy, double *accx, double *accy,
+                                                   int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    accx[c] = (double)fx[c];
+    accy[c] = (double)fy[c];
+}
+
+// Interpolation of a parent-level field to a child centre a quarter parent
+// cell from parent (I, J) towards (sx, sy), from the available parent-level
+// cells: biquadratic on the 3 x 3 block if all of it exists; else bilinear,
+// planar, linear in x, linear in y, or the parent's own value, each tried
+// with the neighbour directions (sx, sy), (-sx, sy), (sx, -sy), (-sx, -sy)
+// in that order.  av(a, b) tells whether parent (I + a, J + b) exists.
+// Writes up to 9 (a, b, weight) and returns the count.
+struct StencilTerm {
+    int a, b;
+    double w;
+};
+template <class AV> __device__ int nest_stencil(const AV &av, int sx, int sy, StencilTerm *st) {
+    bool all = true;
+    for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a) all = all && av(a, b);
+    if (all) {
+        int n = 0;
+        for (int b = -1; b <= 1; ++b) {
+            const double wy = b == 0 ? 15.0 / 16.0 : (b == sy ? 5.0 / 32.0 : -3.0 / 32.0);
+            for (int a = -1; a <= 1; ++a) {
+                const double wx = a == 0 ? 15.0 / 16.0 : (a == sx ? 5.0 / 32.0 : -3.0 / 32.0);
+                st[n++] = StencilTerm{a, b, wx * wy};
+            }
+        }
+        return n;
+    }
+    const int dxs[4] = {sx, -sx, sx, -sx}, dys[4] = {sy, sy, -sy, -sy};
+    for (int d = 0; d < 4; ++d) {
+        const int ex = dxs[d], ey = dys[d];
+        if (av(ex, 0) && av(0, ey) && av(ex, ey)) {
+            const double al = sx * ex / 4.0, be = sy * ey / 4.0;
+            st[0] = StencilTerm{0, 0, (1 - al) * (1 - be)};
+            st[1] = StencilTerm{ex, 0, al * (1 - be)};
+            st[2] = StencilTerm{0, ey, (1 - al) * be};
+            st[3] = StencilTerm{ex, ey, al * be};
+            return 4;
+        }
+    }
+    for (int d = 0; d < 4; ++d) {
+        const int ex = dxs[d], ey = dys[d];
+        if (av(ex, 0) && av(0, ey)) {
+            const double al = sx * ex / 4.0, be = sy * ey / 4.0;
+            st[0] = StencilTerm{0, 0, 1 - al - be};
+            st[1] = StencilTerm{ex, 0, al};
+            st[2] = StencilTerm{0, ey, be};
+            return 3;
+        }
+    }
+    for (int ex = sx, k = 0; k < 2; ++k, ex = -ex) {
+        if (av(ex, 0)) {
+            const double al = sx * ex / 4.0;
+            st[0] = StencilTerm{0, 0, 1 - al};
+            st[1] = StencilTerm{ex, 0, al};
+            return 2;
+        }
+    }
+    for (int ey = sy, k = 0; k < 2; ++k, ey = -ey) {
+        if (av(0, ey)) {
+            const double be = sy * ey / 4.0;
+            st[0] = StencilTerm{0, 0, 1 - be};
+            st[1] = StencilTerm{0, ey, be};
+            return 2;
+        }
+    }
+    st[0] = StencilTerm{0, 0, 1.0};
+    return 1;
+}
+
+// One thread per cell of a box: level-l cells of the box get
+// F^l = F_fine + sum_k w_k (F^{l-1}(p_k) - F_coarse(p_k)) in FP64.
+template <typename T> __global__ void __launch_bounds__(256) k_nest_combine(CombineArgs<T> a) {
+    const int b = blockIdx.y;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nbox || idx >= kNestBox * kNestBox) return;
+    const int tx = idx % kNestBox, ty = idx / kNestBox;
+    const int fxl = tx + kNestExt, fyl = ty + kNestExt;  // position in the fine region
+    const int64_t fo = (int64_t)b * kNestFine * kNestFine + (int64_t)fyl * kNestFine + fxl;
+    const int32_t o = a.fown[fo];
+    const int32_t c = o & 0x0FFFFFFF;
+    if (c == a.sentinel || (o >> 28) != 0) return;  // no level-l cell here
+    // box origins are multiples of kNestBox, so cell parity and the parent's
+    // place in the coarse region follow from the position in the box
+    const int sx = (tx & 1) ? 1 : -1, sy = (ty & 1) ? 1 : -1;
+    const int ci = (tx >> 1) + kNestExt / 2, cj = (ty >> 1) + kNestExt / 2;
+    const int32_t *cown = a.cown + (int64_t)b * kNestCoarse * kNestCoarse;
+    auto av = [&](int da, int db) {
+        const int32_t q = cown[(cj + db) * kNestCoarse + ci + da];
+        return (q & 0x0FFFFFFF) != a.sentinel && (q >> 28) == 0;
+    };
+    StencilTerm st[9];
+    const int n = nest_stencil(av, sx, sy, st);
+    const T *cfx = a.cfx + (int64_t)b * kNestCoarse * kNestCoarse;
+    const T *cfy = a.cfy + (int64_t)b * kNestCoarse * kNestCoarse;
+    double ex = 0.0, ey = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int pos = (cj + st[k].b) * kNestCoarse + ci + st[k].a;
+        const int32_t pc = cown[pos] & 0x0FFFFFFF;
+        ex += st[k].w * (a.accx[pc] - (double)cfx[pos]);
+        ey += st[k].w * (a.accy[pc] - (double)cfy[pos]);
+    }
+    a.accx[c] = (double)a.ffx[fo] + ex;
+    a.accy[c] = (double)a.ffy[fo] + ey;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_nest_finalize(const double *accx, const double *accy,
+                                                       const uint8_t *leaf, T *fx, T *fy, int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const bool l = leaf[c] != 0;
+    fx[c] = l ? (T)accx[c] : (T)0;
+    fy[c] = l ? (T)accy[c] : (T)0;
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -338,6 +500,48 @@ hipError_t launch_col_extract(const C<double> *in, int M, TQ *q, int64_t q_pitch
                               hipStream_t s) {
     GRAV_SWITCH_M(M, return (col_extract_m<TQ, MM>(in, q, q_pitch, imag, corner, tw, ph, s)))
 }
+
+static unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+hipError_t launch_nest_copy_in(const T *s, const T *dx, const T *dy, T *rs, T *rdx, T *rdy, int64_t n,
+                               hipStream_t st) {
+    hipLaunchKernelGGL((k_nest_copy_in<T>), dim3(nblocks(n + 1)), dim3(256), 0, st, s, dx, dy, rs, rdx, rdy, n);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_nest_restrict(const RestrictArgs<T> &a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_nest_restrict<T>), dim3(nblocks(a.n)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_nest_lift(const T *fx, const T *fy, double *accx, double *accy, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_nest_lift<T>), dim3(nblocks(n)), dim3(256), 0, st, fx, fy, accx, accy, n);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_nest_combine(const CombineArgs<T> &a, hipStream_t st) {
+    if (a.nbox <= 0) return hipSuccess;
+    if (a.nbox > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_nest_combine<T>), dim3(kNestBox * kNestBox / 256, a.nbox), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_nest_finalize(const double *accx, const double *accy, const uint8_t *leaf, T *fx, T *fy,
+                                int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_nest_finalize<T>), dim3(nblocks(n)), dim3(256), 0, st, accx, accy, leaf, fx, fy, n);
+    return hipGetLastError();
+}
+#define GRAV_NEST_INST(T)                                                                                   \
+    template hipError_t launch_nest_copy_in<T>(const T *, const T *, const T *, T *, T *, T *, int64_t,     \
+                                               hipStream_t);                                                \
+    template hipError_t launch_nest_restrict<T>(const RestrictArgs<T> &, hipStream_t);                      \
+    template hipError_t launch_nest_lift<T>(const T *, const T *, double *, double *, int64_t, hipStream_t); \
+    template hipError_t launch_nest_combine<T>(const CombineArgs<T> &, hipStream_t);                        \
+    template hipError_t launch_nest_finalize<T>(const double *, const double *, const uint8_t *, T *, T *,   \
+                                                int64_t, hipStream_t);
+GRAV_NEST_INST(float)
+GRAV_NEST_INST(double)
+#undef GRAV_NEST_INST
 
 template hipError_t launch_gather<float>(const Pack<GatherArgs<float>> &, int, int64_t, hipStream_t);
 template hipError_t launch_gather<double>(const Pack<GatherArgs<double>> &, int, int64_t, hipStream_t);

@@ -4,6 +4,6 @@
 namespace grav {
 
 template hipError_t launch_col<float>(const Pack<ColArgs<float>> &, int, int, int, int, int, int,
-                                    const C<float> *, const C<float> *, hipStream_t);
+                                    const C<float> *, const C<float> *, hipStream_t, int);
 
 }  // namespace grav

@@ -4,6 +4,6 @@
 namespace grav {
 
 template hipError_t launch_col<double>(const Pack<ColArgs<double>> &, int, int, int, int, int, int,
-                                    const C<double> *, const C<double> *, hipStream_t);
+                                    const C<double> *, const C<double> *, hipStream_t, int);
 
 }  // namespace grav

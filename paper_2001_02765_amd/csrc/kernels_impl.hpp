@@ -114,7 +114,9 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
     const int r = t % RPB, tr = t / RPB;
-    const int64_t j = (int64_t)xcd_row_group(blockIdx.x, gridDim.x) * RPB + r;
+    const int64_t grp = xcd_row_group(blockIdx.x, gridDim.x);
+    if (grp * RPB >= a.nrows) return;  // whole block: beyond this item's rows
+    const int64_t j = grp * RPB + r;
     const LdsAoS map{RPB, r};
     const C<T> *__restrict__ hw = tw + M;  // exp(-i pi (2k+1)/M)
     TwReg<T, L, NTR> twr;
@@ -362,10 +364,14 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
 template <typename T, int M, int V, int NF, int NFAM, int NC>
 __global__ void __launch_bounds__((M / col_e(V)))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
+    ColArgs<T> a = pk.a[blockIdx.z];
+    if ((int)blockIdx.y >= a.nsub) return;  // whole block: beyond this item's sub-items
+    a.in += (int64_t)blockIdx.y * a.sub_off;
+    a.out += (int64_t)blockIdx.y * a.sub_off;
     if constexpr (var_dbl(V))
-        col2_body<T, M, V, NF, NFAM, NC>(pk.a[blockIdx.z], tw, ph);
+        col2_body<T, M, V, NF, NFAM, NC>(a, tw, ph);
     else
-        col_body<T, M, V, NF, NFAM, NC>(pk.a[blockIdx.z], tw, ph);
+        col_body<T, M, V, NF, NFAM, NC>(a, tw, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,7 +391,9 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
     __shared__ C<T> lds[RPB * CF::SLOTS];
     const int t = threadIdx.x;
     const int r = t % RPB, tr = t / RPB;
-    const int64_t j = (int64_t)xcd_row_group(blockIdx.x, gridDim.x) * RPB + r;
+    const int64_t grp = xcd_row_group(blockIdx.x, gridDim.x);
+    if (grp * RPB >= a.nrows) return;  // whole block: beyond this item's rows
+    const int64_t j = grp * RPB + r;
     const LdsAoS map{RPB, r};
     const C<T> *__restrict__ hw = tw + M;  // exp(-i pi (2k+1)/M)
     TwReg<T, L, NTR> twr;
@@ -444,14 +452,16 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
 
 template <typename T, int M> struct Dispatch {
     template <int V>
-    static hipError_t row_fwd_v(const Pack<RowFwdArgs<T>> &a, int n, bool pruned, int nrows,
+    static hipError_t row_fwd_v(const Pack<RowFwdArgs<T>> &a, int n, bool pruned, int64_t nrows,
                                 int nfields, const C<T> *tw, hipStream_t s) {
         if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
         } else {
             using CF = RowCfg<T, M, var_e(V), row_scale(V)>;
-            if (nrows % CF::RPB) return hipErrorInvalidValue;
-            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nfields, n);
+            if (nrows % CF::RPB || nrows / CF::RPB > 0x7FFFFFFF) return hipErrorInvalidValue;
+            for (int i = 0; i < n; ++i)
+                if (a.a[i].nrows % CF::RPB || a.a[i].nrows > nrows) return hipErrorInvalidValue;
+            dim3 grid((unsigned)(nrows / CF::RPB), var_all(V) ? 1 : nfields, n);
             if (pruned && a.a[0].owner)  // AMR: every item of a pack shares the layout kind
                 hipLaunchKernelGGL((k_row_fwd<T, M, V, true, true>), grid, dim3(CF::NTH), 0, s, a, nfields, tw);
             else if (pruned)
@@ -463,7 +473,7 @@ template <typename T, int M> struct Dispatch {
             return hipGetLastError();
         }
     }
-    static hipError_t row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int var, bool pruned, int nrows,
+    static hipError_t row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int var, bool pruned, int64_t nrows,
                               int nfields, const C<T> *tw, hipStream_t s) {
         switch (var) {
             case 0: return row_fwd_v<0>(a, n, pruned, nrows, nfields, tw, s);
@@ -483,60 +493,65 @@ template <typename T, int M> struct Dispatch {
     }
     template <int V, int NF, int NFAM, int NC>
     static hipError_t col_v(const Pack<ColArgs<T>> &a, int n, const C<T> *tw, const C<T> *ph,
-                            hipStream_t s) {
+                            hipStream_t s, int nsub) {
         if constexpr (!col_var_ok<T, M, V, NF, NFAM, NC>()) {
             return hipErrorInvalidValue;
         } else {
+            if (nsub < 1 || nsub > 65535) return hipErrorInvalidValue;
+            for (int i = 0; i < n; ++i)
+                if (a.a[i].nsub < 1 || a.a[i].nsub > nsub) return hipErrorInvalidValue;
             const unsigned nblk = var_dbl(V) ? M / 4 : M / 2;
-            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, 1, n), dim3(M / col_e(V)), 0, s,
+            hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, nsub, n), dim3(M / col_e(V)), 0, s,
                                a, tw, ph);
             return hipGetLastError();
         }
     }
     template <int V, int NC>
     static hipError_t col_nc(const Pack<ColArgs<T>> &a, int n, int nfields, int nfam, const C<T> *tw,
-                             const C<T> *ph, hipStream_t s) {
-        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1, NC>(a, n, tw, ph, s);
-        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2, NC>(a, n, tw, ph, s);
-        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1, NC>(a, n, tw, ph, s);
-        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2, NC>(a, n, tw, ph, s);
+                             const C<T> *ph, hipStream_t s, int nsub) {
+        if (nfields == 3 && nfam == 1) return col_v<V, 3, 1, NC>(a, n, tw, ph, s, nsub);
+        if (nfields == 3 && nfam == 2) return col_v<V, 3, 2, NC>(a, n, tw, ph, s, nsub);
+        if (nfields == 1 && nfam == 1) return col_v<V, 1, 1, NC>(a, n, tw, ph, s, nsub);
+        if (nfields == 1 && nfam == 2) return col_v<V, 1, 2, NC>(a, n, tw, ph, s, nsub);
         return hipErrorInvalidValue;
     }
     template <int V>
     static hipError_t col_nf(const Pack<ColArgs<T>> &a, int n, int nfields, int nfam, int ncomp,
-                             const C<T> *tw, const C<T> *ph, hipStream_t s) {
-        if (ncomp == 2) return col_nc<V, 2>(a, n, nfields, nfam, tw, ph, s);
-        if (ncomp == 3) return col_nc<V, 3>(a, n, nfields, nfam, tw, ph, s);
+                             const C<T> *tw, const C<T> *ph, hipStream_t s, int nsub) {
+        if (ncomp == 2) return col_nc<V, 2>(a, n, nfields, nfam, tw, ph, s, nsub);
+        if (ncomp == 3) return col_nc<V, 3>(a, n, nfields, nfam, tw, ph, s, nsub);
         return hipErrorInvalidValue;
     }
     static hipError_t col(const Pack<ColArgs<T>> &a, int n, int var, int nfields, int nfam, int ncomp,
-                          const C<T> *tw, const C<T> *ph, hipStream_t s) {
+                          const C<T> *tw, const C<T> *ph, hipStream_t s, int nsub) {
         switch (var) {
-            case 0: return col_nf<0>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 1: return col_nf<1>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 2: return col_nf<2>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 3: return col_nf<3>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 4: return col_nf<4>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 6: return col_nf<6>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 8: return col_nf<8>(a, n, nfields, nfam, ncomp, tw, ph, s);
-            case 9: return col_nf<9>(a, n, nfields, nfam, ncomp, tw, ph, s);
+            case 0: return col_nf<0>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 1: return col_nf<1>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 2: return col_nf<2>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 3: return col_nf<3>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 4: return col_nf<4>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 6: return col_nf<6>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 8: return col_nf<8>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 9: return col_nf<9>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
         }
         return hipErrorInvalidValue;
     }
     template <int V>
-    static hipError_t row_inv_v(const Pack<RowInvArgs<T>> &a, int n, int nrows, int nout,
+    static hipError_t row_inv_v(const Pack<RowInvArgs<T>> &a, int n, int64_t nrows, int nout,
                                 const C<T> *tw, hipStream_t s) {
         if constexpr (!row_var_ok<T, M, V>()) {
             return hipErrorInvalidValue;
         } else {
             using CF = RowCfg<T, M, var_e(V), row_scale(V)>;
-            if (nrows % CF::RPB) return hipErrorInvalidValue;
-            dim3 grid(nrows / CF::RPB, var_all(V) ? 1 : nout, n);
+            if (nrows % CF::RPB || nrows / CF::RPB > 0x7FFFFFFF) return hipErrorInvalidValue;
+            for (int i = 0; i < n; ++i)
+                if (a.a[i].nrows % CF::RPB || a.a[i].nrows > nrows) return hipErrorInvalidValue;
+            dim3 grid((unsigned)(nrows / CF::RPB), var_all(V) ? 1 : nout, n);
             hipLaunchKernelGGL((k_row_inv<T, M, V>), grid, dim3(CF::NTH), 0, s, a, nout, tw);
             return hipGetLastError();
         }
     }
-    static hipError_t row_inv(const Pack<RowInvArgs<T>> &a, int n, int var, int nrows, int nout,
+    static hipError_t row_inv(const Pack<RowInvArgs<T>> &a, int n, int var, int64_t nrows, int nout,
                               const C<T> *tw, hipStream_t s) {
         switch (var) {
             case 0: return row_inv_v<0>(a, n, nrows, nout, tw, s);
@@ -558,18 +573,18 @@ template <typename T, int M> struct Dispatch {
 
 template <typename T>
 hipError_t launch_row_fwd(const Pack<RowFwdArgs<T>> &a, int n, int M, int var, bool pruned,
-                          int nrows, int nfields, const C<T> *tw, hipStream_t s) {
+                          int64_t nrows, int nfields, const C<T> *tw, hipStream_t s) {
     if (n < 1 || n > kPack) return hipErrorInvalidValue;
     GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_fwd(a, n, var, pruned, nrows, nfields, tw, s)))
 }
 template <typename T>
 hipError_t launch_col(const Pack<ColArgs<T>> &a, int n, int M, int var, int nfields, int nfam,
-                      int ncomp, const C<T> *tw, const C<T> *ph, hipStream_t s) {
+                      int ncomp, const C<T> *tw, const C<T> *ph, hipStream_t s, int nsub) {
     if (n < 1 || n > kPack) return hipErrorInvalidValue;
-    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, n, var, nfields, nfam, ncomp, tw, ph, s)))
+    GRAV_SWITCH_M(M, return (Dispatch<T, MM>::col(a, n, var, nfields, nfam, ncomp, tw, ph, s, nsub)))
 }
 template <typename T>
-hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int nrows, int nout,
+hipError_t launch_row_inv(const Pack<RowInvArgs<T>> &a, int n, int M, int var, int64_t nrows, int nout,
                           const C<T> *tw, hipStream_t s) {
     if (n < 1 || n > kPack) return hipErrorInvalidValue;
     GRAV_SWITCH_M(M, return (Dispatch<T, MM>::row_inv(a, n, var, nrows, nout, tw, s)))

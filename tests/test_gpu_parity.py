@@ -661,3 +661,33 @@ def test_solve_replays_from_a_hip_graph(gl):
         # eager work between replays
         cases[0][0].solve(*cases[0][1], fx=cases[0][2][0], fy=cases[0][2][1], workspace=cases[0][3])
         torch.cuda.synchronize()
+
+
+def test_server_waits_for_the_callers_stream(gl):
+    """Inputs still being written on the caller's stream when the request is
+    submitted: the server's work waits for that stream (an event recorded at
+    submit), so the result is the solve of the final inputs."""
+    n = 256
+    p = gl.Plan(n, gl.F32)
+    s, dx, dy, h = diskgen.noisy_spiral(n, 5)
+    final = [_dev(a, "f32") for a in (s, dx, dy)]
+    ref = p.solve(*final)
+    torch.cuda.synchronize()
+    srv = gl.Server(4 * p.workspace_bytes, nstreams=2)
+    side = torch.cuda.Stream()
+    big = torch.randn(4096, 4096, device="cuda")
+    outs = []
+    for rep in range(3):
+        ins = [torch.zeros_like(t) for t in final]
+        o = (torch.full_like(final[0], float("nan")), torch.full_like(final[0], float("nan")))
+        with torch.cuda.stream(side):
+            for _ in range(4):               # keep the side stream busy first
+                big = (big @ big).tanh_()
+            for t, f in zip(ins, final):
+                t.copy_(f)
+            tk = srv.submit(p, *ins, *o, stream=side)
+        outs.append((tk, ins, o))
+    for tk, ins, o in outs:
+        srv.wait(tk)
+        assert torch.equal(o[0], ref[0]) and torch.equal(o[1], ref[1])
+    srv.close()
