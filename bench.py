@@ -7,9 +7,12 @@ seeded Gaussian noise and central-difference slopes, inputs resident in HBM.
 The FP32 path is the headline value; the FP64 path, p50/p99 per-solve
 latency, the per-stage roofline of the dominant kernel, the whole-solve
 roofline under the compulsory and two-pass byte models, the spread over the
-disks of seeds 0-4, the AMR, off-plane, batched and served workloads (each
-beside the plain FP64 path) and the CPU oracle's rate on bounded samples are
-reported on the same JSON line.
+disks of seeds 0-4, the 2048^2-cell reading of the headline size, the exact
+and nested-correction AMR workloads, the off-plane, batched and served
+workloads (each beside the plain FP64 path), the achieved error of every
+result against the FP64 oracle (relative L2 and max|dF|/max|F| on seeded
+target samples) and the CPU oracle's rate on bounded samples are reported on
+the same JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -40,6 +43,69 @@ def col_bytes(n, prec_bytes, nfields=3, nfam=1):
     q = nfam * 6 * cols * (m // 2 + 1) * prec_bytes
     b = 2 * nfam * cols * n * cplx
     return a + q + b
+
+
+def accuracy(got, ref, area=None, what=""):
+    """Achieved error of GPU results against FP64 oracle values at the same
+    targets: area-weighted relative L2 over all components, and
+    max |dF| / max |F|."""
+    a = 1.0 if area is None else np.asarray(area, dtype=np.float64)
+    num = den = 0.0
+    mx = mref = 0.0
+    for g, r in zip(got, ref):
+        g = np.asarray(g, dtype=np.float64)
+        r = np.asarray(r, dtype=np.float64)
+        num += float(np.sum((g - r) ** 2 * a))
+        den += float(np.sum(r * r * a))
+        mx = max(mx, float(np.max(np.abs(g - r))))
+        mref = max(mref, float(np.max(np.abs(r))))
+    return {"rel_l2": float(np.sqrt(num / den)), "max_rel": mx / mref, "targets": int(np.size(ref[0])),
+            "against": what}
+
+
+def _rects_uniform(n, h):
+    e = -1.0 + h * np.arange(n)
+    X, Y = np.meshgrid(e, e)
+    rect = np.stack([X.ravel(), X.ravel() + h, Y.ravel(), Y.ravel() + h], 1)
+    cent = np.stack([X.ravel() + 0.5 * h, Y.ravel() + 0.5 * h], 1)
+    return rect, cent
+
+
+def uniform_accuracy(fields, n, fx, fy, k, seed):
+    """GPU uniform-grid result against the oracle's direct sum over every
+    source cell at k seeded target cells (plus the four corner cells)."""
+    import oracle
+    s, dx, dy, h = fields
+    rng = np.random.default_rng(seed)
+    tg = np.unique(np.concatenate([rng.choice(n * n, k, replace=False), [0, n - 1, n * (n - 1), n * n - 1]]))
+    ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, h, targets=tg, threads=len(os.sched_getaffinity(0)))
+    got = (fx.double().cpu().numpy()[tg], fy.double().cpu().numpy()[tg])
+    return accuracy(got, (ox, oy), what="oracle direct sum over every cell (FP64), %d seeded cells" % len(tg))
+
+
+def leaf_targets(lay, per_level, seed):
+    """Seeded leaf sample, per_level leaves of every leaf size."""
+    import oracle
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    size = rect[:, 1] - rect[:, 0]
+    rng = np.random.default_rng(seed)
+    sel = []
+    for hv in np.unique(size):
+        cand = np.nonzero(size == hv)[0]
+        sel.extend(rng.choice(cand, min(per_level, len(cand)), replace=False))
+    return rect, cent, idx, np.array(sorted(sel))
+
+
+def amr_accuracy(lay, vals, fx, fy, per_level, seed, what="oracle leaf direct sum (FP64)"):
+    """GPU AMR result against the exact leaf-by-leaf direct sum at sampled
+    leaves of every level (area weighted)."""
+    import oracle
+    s, dx, dy = vals
+    rect, cent, idx, sel = leaf_targets(lay, per_level, seed)
+    ox, oy = oracle.direct(rect, s[idx], dx[idx], dy[idx], cent[sel], threads=len(os.sched_getaffinity(0)))
+    area = (rect[sel, 1] - rect[sel, 0]) ** 2
+    got = (fx.double().cpu().numpy()[idx[sel]], fy.double().cpu().numpy()[idx[sel]])
+    return accuracy(got, (ox, oy), area, what="%s, %d leaves over every level" % (what, len(sel)))
 
 
 # HBM traffic of the column kernel, measured with rocprofv3 counters
@@ -75,7 +141,16 @@ def stored_traffic(kernel, n):
     return None
 
 
-def run_precision(gl, torch, prec, n, steps, warmup, fields, latency=True):
+def progress(msg, _t0=[None]):
+    """One line per finished leg on stderr (the JSON result stays the only
+    line on stdout)."""
+    now = time.perf_counter()
+    if _t0[0] is None:
+        _t0[0] = now
+    print("bench: %s (%.1f s)" % (msg, now - _t0[0]), file=sys.stderr, flush=True)
+
+
+def run_precision(gl, torch, prec, n, steps, warmup, fields, latency=True, acc=True):
     dt = torch.float64 if prec == gl.F64 else torch.float32
     s, dx, dy, h = fields
     plan = gl.Plan(n, prec, h0=h)
@@ -106,12 +181,14 @@ def run_precision(gl, torch, prec, n, steps, warmup, fields, latency=True):
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
     stages = plan.profile(*t, fx, fy, ws, reps=steps, stream=stream)
+    torch.cuda.synchronize()
     return {
         "value": n * n / (ms * 1e-3),
         "ms_per_step": ms,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "stages_ms": stages,
         "variants": list(plan.variants),
+        **({"accuracy": uniform_accuracy(fields, n, fx, fy, 256, 2024 + prec)} if acc else {}),
     }
 
 
@@ -126,63 +203,147 @@ def _timeit(torch, fn, reps):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
+def _col_frac(n, prec_bytes, ms, nfam=1):
+    """Column-kernel HBM fraction from the col_bytes model and a measured
+    mean launch time."""
+    gbs = col_bytes(n, prec_bytes, 3, nfam) / (ms * 1e-3) / 1e9
+    return {"achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": col_bytes(n, prec_bytes, 3, nfam),
+            "launch_ms": ms}
+
+
 def amr_leg(gl, torch, reps):
-    """3-level AMR workload (base 256^2, finest 1024^2): leaf forces/s."""
+    """3-level AMR workload (base 256^2, finest 1024^2): leaf forces/s of the
+    exact path (FP32, FP64) and of the nested-correction path, each with its
+    error against the exact leaf sum and the column kernel's HBM fraction."""
     import diskgen
     lay, s, dx, dy = diskgen.amr_config(0)
     out = {"workload": "AMR 3 levels, base 256^2, %d patches of 32^2, finest lattice 1024^2 "
                        "(2048^2 FFT), Kuzmin a=0.02 + clumps" % len(lay.patches),
            "leaves": lay.nleaves()}
-    for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
-        p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches)
+    for name, prec, dt, amr in (("f32", gl.F32, torch.float32, "exact"), ("f64", gl.F64, torch.float64, "exact"),
+                                ("nested_f32", gl.F32, torch.float32, "nested"),
+                                ("nested_f64", gl.F64, torch.float64, "nested")):
+        p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches, amr=amr)
         t = [torch.from_numpy(a).to("cuda", dt) for a in (s, dx, dy)]
         fx = torch.empty(p.n_cells, dtype=dt, device="cuda")
         fy = torch.empty_like(fx)
         ws = p.workspace()
         ms = _timeit(torch, lambda: p.solve(*t, fx=fx, fy=fy, workspace=ws), reps)
-        out[name] = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3),
-                     "stages_ms": p.profile(*t, fx, fy, ws, reps=max(5, reps // 4))}
+        r = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3)}
+        if amr == "exact":
+            r["stages_ms"] = p.profile(*t, fx, fy, ws, reps=max(5, reps // 4))
+            r["col_roofline"] = _col_frac(p.n_finest, 4 if prec == gl.F32 else 8, r["stages_ms"]["col"], 2)
+        torch.cuda.synchronize()
+        r["accuracy"] = amr_accuracy(lay, (s, dx, dy), fx, fy, 24, 5,
+                                     what="exact leaf direct sum (FP64)" + (": the nested scheme's deviation"
+                                                                           if amr == "nested" else ""))
+        out[name] = r
     return out
 
 
 def paper_amr_leg(gl, torch, reps):
-    """The largest AMR experiment of the paper's Section 3 that this path
-    runs: AMR(3, D2) under independent level refinement at N_k = 1024 (1.42M
-    leaves, finest lattice 4096^2, 8192^2 FFT), FP32 and FP64.  Table 8
-    times the same case with the direct sum on a P100 at 1.05e3 s (context:
-    another algorithm on other hardware)."""
+    """The largest AMR experiment of the paper's Section 3: AMR(3, D2) under
+    independent level refinement at N_k = 1024 (1.42M leaves, finest lattice
+    4096^2), by the exact path (8192^2 FFT) and the nested-correction path,
+    FP32 and FP64.  Table 8 times the same case with the direct sum on a
+    P100 at 1.05e3 s (context: another algorithm on other hardware)."""
     import diskgen
     lay = diskgen.ilr_layout(1024, 3, "d2")
     s, dx, dy = lay.sample(diskgen.d2)
     out = {"workload": "AMR(3, D2) ILR, N_k = 1024: %d leaves in %d patches, finest lattice %d^2"
                        % (lay.nleaves(), len(lay.patches), lay.n_finest),
            "leaves": lay.nleaves(), "paper_p100_direct_s": 1.05e3}
-    for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
-        p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches)
+    for name, prec, dt, amr in (("f32", gl.F32, torch.float32, "exact"), ("f64", gl.F64, torch.float64, "exact"),
+                                ("nested_f32", gl.F32, torch.float32, "nested"),
+                                ("nested_f64", gl.F64, torch.float64, "nested")):
+        p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches, amr=amr)
         t = [torch.from_numpy(a).to("cuda", dt) for a in (s, dx, dy)]
         fx = torch.empty(p.n_cells, dtype=dt, device="cuda")
         fy = torch.empty_like(fx)
         ws = p.workspace()
         ms = _timeit(torch, lambda: p.solve(*t, fx=fx, fy=fy, workspace=ws), reps)
-        out[name] = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3)}
+        r = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3)}
+        if amr == "exact":
+            st = p.profile(*t, fx, fy, ws, reps=3)
+            r["stages_ms"] = st
+            r["col_roofline"] = _col_frac(p.n_finest, 4 if prec == gl.F32 else 8, st["col"], 2)
+        torch.cuda.synchronize()
+        r["accuracy"] = amr_accuracy(lay, (s, dx, dy), fx, fy, 16, 6,
+                                     what="exact leaf direct sum (FP64)" + (": the nested scheme's deviation"
+                                                                           if amr == "nested" else ""))
+        out[name] = r
         del p, t, fx, fy, ws
+    return out
+
+
+def nested_leg(gl, torch, reps):
+    """The served stream's largest requests, which only the nested-correction
+    path solves: base 2048^2 with 4 levels (finest lattice 16384^2) and base
+    1024^2 with 4 levels (8192^2), FP32 and FP64: leaf forces/s and the
+    deviation from the exact leaf sum."""
+    import diskgen
+    out = {}
+    for n0 in (2048, 1024):
+        lay, prof = diskgen.request_pool_full(0, bases=(n0,), levels=(4,))[0]
+        s, dx, dy = lay.sample(prof)
+        leg = {"workload": "base %d^2, 4 levels, %d patches of 32^2 (%d leaves), finest lattice %d^2, Kuzmin "
+                           "+ clumps" % (n0, len(lay.patches), lay.nleaves(), lay.n_finest),
+               "leaves": lay.nleaves()}
+        for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
+            p = gl.Plan(lay.n0, prec, nlevels=lay.nlevels, patches=lay.patches, amr="nested")
+            t = [torch.from_numpy(a).to("cuda", dt) for a in (s, dx, dy)]
+            fx = torch.empty(p.n_cells, dtype=dt, device="cuda")
+            fy = torch.empty_like(fx)
+            ws = p.workspace()
+            ms = _timeit(torch, lambda: p.solve(*t, fx=fx, fy=fy, workspace=ws), reps)
+            torch.cuda.synchronize()
+            leg[name] = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3),
+                         "workspace_bytes": p.workspace_bytes,
+                         "accuracy": amr_accuracy(lay, (s, dx, dy), fx, fy, 12, 7,
+                                                  what="exact leaf direct sum (FP64): the nested scheme's "
+                                                       "deviation")}
+            del p, t, fx, fy, ws
+        out["base%d_4levels" % n0] = leg
+    return out
+
+
+def n2048_leg(gl, torch, steps, warmup):
+    """The other reading of "at 2048^2": 2048^2 cells (4096^2 zero-padded
+    FFT), the same disk recipe, FP32 and FP64."""
+    import diskgen
+    n = 2048
+    fields = diskgen.noisy_spiral(n, 0)
+    out = {"workload": "uniform %dx%d cells on [-1,1]^2, zero-padded %d^2 FFT, noisy exponential spiral "
+                       "disk with slopes" % (n, n, 2 * n)}
+    for name, prec, pb in (("f32", gl.F32, 4), ("f64", gl.F64, 8)):
+        r = run_precision(gl, torch, prec, n, steps, warmup, fields)
+        r["col_roofline"] = _col_frac(n, pb, r["stages_ms"]["col"])
+        out[name] = r
     return out
 
 
 def offplane_leg(gl, torch, reps, fields, n):
     """The headline disk with targets at height z = 0.05 above every cell
     centre (25.6 cells at 1024^2): (Fx, Fy, Fz) per cell."""
+    import oracle
     s, dx, dy, h = fields
     z = 0.05
     out = {"workload": "uniform %dx%d cells, zero-padded %d^2 FFT, targets at height z = %g "
                        "above the cell centres, (Fx, Fy, Fz)" % (n, n, 2 * n, z)}
+    rect, cent = _rects_uniform(n, h)
+    tg = np.random.default_rng(55).choice(n * n, 24, replace=False)
+    ref = oracle.direct_z(rect, s.ravel(), dx.ravel(), dy.ravel(), cent[tg], z,
+                          threads=len(os.sched_getaffinity(0)))
     for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
         p = gl.Plan(n, prec, h0=h, z=z)
         t = [torch.from_numpy(a.ravel()).to("cuda", dt) for a in (s, dx, dy)]
         fo = [torch.empty(n * n, dtype=dt, device="cuda") for _ in range(3)]
         ws = p.workspace()
         ms = _timeit(torch, lambda: p.solve_xyz(*t, *fo, workspace=ws), reps)
-        out[name] = {"ms": ms, "forces_per_s": n * n / (ms * 1e-3), "variants": list(p.variants)}
+        torch.cuda.synchronize()
+        out[name] = {"ms": ms, "forces_per_s": n * n / (ms * 1e-3), "variants": list(p.variants),
+                     "accuracy": accuracy([f.double().cpu().numpy()[tg] for f in fo], ref,
+                                          what="oracle off-plane direct sum (FP64), 24 seeded cells")}
     return out
 
 
@@ -190,6 +351,7 @@ def batch_leg(gl, torch, reps):
     """64 independent disks of mixed sizes in one gravity_solve_batch (FP32)
     against the same 64 solves issued one by one."""
     import diskgen
+    import oracle
     disks = diskgen.batch_disks(0)
     plans = [gl.Plan(n, gl.F32) for (n, _, _, _) in disks]
     ins = [[torch.from_numpy(a.ravel()).to("cuda", torch.float32) for a in d[1:]] for d in disks]
@@ -198,6 +360,21 @@ def batch_leg(gl, torch, reps):
     args = ([i[0] for i in ins], [i[1] for i in ins], [i[2] for i in ins],
             [o[0] for o in outs], [o[1] for o in outs])
     ms_b = _timeit(torch, lambda: gl.solve_batch(plans, *args, ws), reps)
+    torch.cuda.synchronize()
+    # achieved error of every disk of the batch at seeded targets
+    rng = np.random.default_rng(64)
+    got, ref = [[], []], [[], []]
+    for (n, s, dx, dy), (fx, fy) in zip(disks, outs):
+        tg = rng.choice(n * n, 3, replace=False)
+        ox, oy = oracle.uniform(s, dx, dy, -1.0, -1.0, 2.0 / n, targets=tg, threads=len(os.sched_getaffinity(0)))
+        scale = 1.0 / max(np.max(np.abs(ox)), np.max(np.abs(oy)))   # each disk weighted alike
+        got[0].append(fx.double().cpu().numpy()[tg] * scale)
+        got[1].append(fy.double().cpu().numpy()[tg] * scale)
+        ref[0].append(ox * scale)
+        ref[1].append(oy * scale)
+    acc = accuracy([np.concatenate(g) for g in got], [np.concatenate(r) for r in ref],
+                   what="oracle direct sum (FP64), 3 seeded cells of each of the 64 disks, each disk scaled to "
+                        "its largest sampled force")
     ws1 = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device="cuda")
 
     def seq():
@@ -215,41 +392,59 @@ def batch_leg(gl, torch, reps):
             p.solve(*i, fx=o[0], fy=o[1], workspace=ws64)
     ms_64 = _timeit(torch, seq64, reps)
     cells = int(sum(d[0] ** 2 for d in disks))
+    two_pass = 124 * cells   # FP32 two-pass byte model, per leaf
     return {"workload": "64 disks, n in {64..1024}, exponential/Kuzmin spirals, FP32",
             "cells": cells, "ms_batch": ms_b, "ms_sequential": ms_s, "ms_sequential_f64": ms_64,
             "forces_per_s_batch": cells / (ms_b * 1e-3), "forces_per_s_sequential": cells / (ms_s * 1e-3),
-            "forces_per_s_sequential_f64": cells / (ms_64 * 1e-3)}
+            "forces_per_s_sequential_f64": cells / (ms_64 * 1e-3),
+            "roofline_two_pass": {"bytes": two_pass, "frac": two_pass / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "accuracy": acc}
 
 
-def serve_leg(gl, torch, nreq, rhos=(0.5, 0.8), budget=8 << 30):
-    """Poisson stream of AMR solves of mixed sizes through the continuous-
-    batching server: closed-loop capacity first, then arrivals at rho times it
-    for each rho; beside it, the plain FP64 path solving the same layouts one
-    at a time."""
+def serve_leg(gl, torch, nreq=2000, warm=200, rhos=(0.5, 0.8), budget=8 << 30):
+    """Poisson stream of AMR solves through the continuous-batching server,
+    over the full request mix (bases 128^2-2048^2, 1-4 levels, 4-256 patches
+    of 32^2): the exact path where the finest lattice is at most 4096^2, the
+    nested-correction path beyond.  Closed-loop capacity first, then
+    arrivals at rho times it for each rho; every in-flight request writes
+    its own outputs.  Beside it, the plain FP64 path solving the same
+    layouts one at a time, and spot checks of served results against the
+    exact leaf sum."""
     import diskgen
-    pool = diskgen.request_pool(0, count=16)
+    pool = diskgen.request_pool_full(0)
     entries = []
+    nslot = 16
     for lay, prof in pool:
-        p = gl.Plan(lay.n0, gl.F32, nlevels=lay.nlevels, patches=lay.patches)
+        amr = "exact" if lay.n_finest <= 4096 else "nested"
+        p = gl.Plan(lay.n0, gl.F32, nlevels=lay.nlevels, patches=lay.patches, amr=amr)
         s, dx, dy = lay.sample(prof)
         t = [torch.from_numpy(a).to("cuda", torch.float32) for a in (s, dx, dy)]
-        outs = [(torch.empty_like(t[0]), torch.empty_like(t[0])) for _ in range(4)]
-        entries.append((p, t, outs, lay))
+        outs = [(torch.empty_like(t[0]), torch.empty_like(t[0])) for _ in range(nslot)]
+        entries.append({"plan": p, "in": t, "outs": outs, "lay": lay, "vals": (s, dx, dy), "amr": amr,
+                        "last": [None] * nslot, "next": 0})
+    torch.cuda.synchronize()
     srv = gl.Server(budget, nstreams=4, max_batch=8)
     rng = np.random.default_rng(1)
-    picks = rng.integers(len(entries), size=nreq)
+    picks = rng.integers(len(entries), size=nreq + warm)
 
     def submit(k):
-        p, t, outs, _ = entries[picks[k]]
-        o = outs[k % len(outs)]
-        return srv.submit(p, *t, o[0], o[1])
+        e = entries[picks[k]]
+        slot = e["next"]
+        e["next"] = (slot + 1) % nslot
+        prev = e["last"][slot]
+        if prev is not None and not srv.poll(prev):
+            srv.wait(prev)   # the slot's previous request must be done with its outputs
+        o = e["outs"][slot]
+        tk = srv.submit(e["plan"], *e["in"], o[0], o[1])
+        e["last"][slot] = tk
+        return tk
 
-    for k in range(min(200, nreq)):  # warm-up
+    for k in range(warm):
         submit(k)
     srv.drain()
     srv.reset_stats()
     t0 = time.perf_counter()
-    for k in range(nreq):
+    for k in range(warm, warm + nreq):
         submit(k)
     srv.drain()
     cap = nreq / (time.perf_counter() - t0)
@@ -264,41 +459,64 @@ def serve_leg(gl, torch, nreq, rhos=(0.5, 0.8), budget=8 << 30):
         for k in range(nreq):
             while time.perf_counter() < t_arr[k]:
                 pass
-            submit(k)
+            submit(warm + k)
         srv.drain()
         wall = time.perf_counter() - t0
         st = srv.stats()
         runs.append({"rho": rho, "rate_req_per_s": lam, "p50_ms": st["latency_p50_ms"],
                      "p99_ms": st["latency_p99_ms"], "max_ms": st["latency_max_ms"],
                      "leaf_forces_per_s": st["leaves_completed"] / wall,
-                     "peak_bytes_in_use": st["peak_bytes_in_use"], "batches": st["batches"]})
+                     "peak_bytes_in_use": st["peak_bytes_in_use"], "batches": st["batches"],
+                     "completed": st["completed"]})
     budget_bytes = srv.stats()["budget_bytes"]
     srv.close()
+    torch.cuda.synchronize()
+    # spot checks: the last served result of a few layouts of each method
+    checks = []
+    for k, e in enumerate(entries):
+        if k % 5 != 2 or e["last"][(e["next"] - 1) % nslot] is None:
+            continue
+        o = e["outs"][(e["next"] - 1) % nslot]
+        a = amr_accuracy(e["lay"], e["vals"], o[0], o[1], 6, 100 + k,
+                         what="exact leaf direct sum (FP64)" + (": nested deviation" if e["amr"] == "nested" else ""))
+        a.update({"base": e["lay"].n0, "levels": e["lay"].nlevels, "method": e["amr"]})
+        checks.append(a)
     # plain FP64 single solves of the same request mix (one stream, one at a
     # time): each layout timed alone, weighted by how often the stream asked for it
-    weights = np.bincount(picks, minlength=len(entries))
+    weights = np.bincount(picks[warm:], minlength=len(entries))
     leaves = ms = 0.0
-    for (_, t, _, lay), w in zip(entries, weights):
-        p = gl.Plan(lay.n0, gl.F64, nlevels=lay.nlevels, patches=lay.patches)
-        t64 = [a.double() for a in t]
+    for e, w in zip(entries, weights):
+        lay = e["lay"]
+        p = gl.Plan(lay.n0, gl.F64, nlevels=lay.nlevels, patches=lay.patches, amr=e["amr"])
+        t64 = [a.double() for a in e["in"]]
         f = (torch.empty_like(t64[0]), torch.empty_like(t64[0]))
         ws = p.workspace()
-        m = _timeit(torch, lambda: p.solve(*t64, fx=f[0], fy=f[1], workspace=ws), 5)
+        m = _timeit(torch, lambda: p.solve(*t64, fx=f[0], fy=f[1], workspace=ws), 3)
         leaves += p.n_leaves * float(w)
         ms += m * float(w)
         del p, t64, f, ws
-    levels = sorted({lay.nlevels for *_, lay in entries})
-    bases = sorted({lay.n0 for *_, lay in entries})
-    npat = [len(lay.patches) for *_, lay in entries if lay.nlevels > 1]
-    finest = max(lay.n0 << (lay.nlevels - 1) for *_, lay in entries)
-    return {"workload": "Poisson arrivals of AMR solves over %d seeded layouts (bases %s, levels %s, "
-                        "%s patches of 32^2 per refined layout, finest lattice up to %d^2), FP32"
-                        % (len(entries), "/".join(map(str, bases)), "/".join(map(str, levels)),
-                           ("%d-%d" % (min(npat), max(npat))) if npat else "no", finest),
-            "requests": nreq, "warmup_requests": min(200, nreq), "capacity_req_per_s": cap,
+    npat = [len(e["lay"].patches) for e in entries if e["lay"].nlevels > 1]
+    return {"workload": "Poisson arrivals of AMR solves over %d seeded layouts (bases 128^2-2048^2, levels 1-4, "
+                        "%d-%d patches of 32^2 per refined layout, finest lattice up to %d^2; exact path for "
+                        "%d layouts with finest <= 4096^2, nested-correction path for %d beyond), FP32"
+                        % (len(entries), min(npat), max(npat), max(e["lay"].n_finest for e in entries),
+                           sum(e["amr"] == "exact" for e in entries), sum(e["amr"] == "nested" for e in entries)),
+            "requests": nreq, "warmup_requests": warm, "unsupported_requests": 0,
+            "capacity_req_per_s": cap,
             "closed_loop_p50_ms": closed["latency_p50_ms"], "closed_loop_p99_ms": closed["latency_p99_ms"],
             "budget_bytes": budget_bytes, "open_loop": runs,
-            "plain_f64_leaf_forces_per_s": leaves / (ms * 1e-3)}
+            "plain_f64_leaf_forces_per_s": leaves / (ms * 1e-3), "accuracy_spot_checks": checks}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(n, fields, budget_s=25.0, with_amr=True):
@@ -308,7 +526,7 @@ def cpu_baseline(n, fields, budget_s=25.0, with_amr=True):
     import oracle
 
     s, dx, dy, h = fields
-    lay_rect, cent = _uniform_rects(n, h)
+    lay_rect, cent = _rects_uniform(n, h)
     rng = np.random.default_rng(7)
     threads = len(os.sched_getaffinity(0))
 
@@ -335,7 +553,7 @@ def cpu_baseline(n, fields, budget_s=25.0, with_amr=True):
     t64 = time.perf_counter()
     oracle.uniform(ks, kdx, kdy, -1.0, -1.0, 2.0 / 64, threads=threads)
     el64 = time.perf_counter() - t64
-    return {"value": k / el, "unit": "forces/s", "cores": threads, "kind": "oracle",
+    return {"value": k / el, "unit": "forces/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "%d seeded target cells of the %dx%d disk, each summed over all %d source "
                       "cells with the exact kernels (direct method), %.1f s" % (k, n, n, n * n, el),
             "value_1core": 4 / el1, "sample_1core": "4 target cells on one thread, %.1f s" % el1,
@@ -421,14 +639,6 @@ def copy_gbs(torch, nbytes=1 << 30, reps=10):
     return gbs
 
 
-def _uniform_rects(n, h):
-    e = -1.0 + h * np.arange(n)
-    X, Y = np.meshgrid(e, e)
-    rect = np.stack([X.ravel(), X.ravel() + h, Y.ravel(), Y.ravel() + h], 1)
-    cent = np.stack([X.ravel() + 0.5 * h, Y.ravel() + 0.5 * h], 1)
-    return rect, cent
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,11 +677,14 @@ def main():
     fields = diskgen.noisy_spiral(n, 0)
     if args.only:
         prec = gl.F32 if args.only == "f32" else gl.F64
-        r = run_precision(gl, torch, prec, n, args.steps, args.warmup, fields)
+        r = run_precision(gl, torch, prec, n, args.steps, args.warmup, fields, acc=False)
         print(json.dumps({"only": args.only, "n": n, **r}), flush=True)
         return
+    progress("start")
     r32 = run_precision(gl, torch, gl.F32, n, args.steps, args.warmup, fields)
+    progress("headline FP32")
     r64 = run_precision(gl, torch, gl.F64, n, args.steps, args.warmup, fields)
+    progress("headline FP64")
 
     col_ms = r32["stages_ms"]["col"]
     achieved = col_bytes(n, 4) / (col_ms * 1e-3) / 1e9
@@ -501,6 +714,7 @@ def main():
                                "exponential spiral disk with slopes" % (n, n, 2 * n),
                    "n": n, "fft": 2 * n, "slopes": True},
         "latency_ms": r32["latency_ms"],
+        "accuracy": r32["accuracy"],
         "stages_ms": r32["stages_ms"],
         "variants": r32["variants"],
         "fp64": r64,
@@ -508,14 +722,21 @@ def main():
         "solve_roofline": solve_roofline(n, r32["ms_per_step"], r64["ms_per_step"]),
     }
     if not args.no_extra:
-        out["seed_spread"] = seed_spread(gl, torch, n, max(20, args.steps // 2), args.warmup, r32["value"])
-        out["amr"] = amr_leg(gl, torch, max(10, args.steps // 4))
-        out["paper_amr"] = paper_amr_leg(gl, torch, max(5, args.steps // 20))
-        out["offplane"] = offplane_leg(gl, torch, max(10, args.steps // 4), fields, n)
-        out["batch"] = batch_leg(gl, torch, max(5, args.steps // 20))
-        out["serve"] = serve_leg(gl, torch, nreq=max(200, 10 * args.steps))
+        legs = (("seed_spread", lambda: seed_spread(gl, torch, n, max(20, args.steps // 2), args.warmup,
+                                                    r32["value"])),
+                ("n2048", lambda: n2048_leg(gl, torch, max(10, args.steps // 4), 5)),
+                ("amr", lambda: amr_leg(gl, torch, max(10, args.steps // 4))),
+                ("paper_amr", lambda: paper_amr_leg(gl, torch, max(5, args.steps // 20))),
+                ("nested", lambda: nested_leg(gl, torch, max(5, args.steps // 20))),
+                ("offplane", lambda: offplane_leg(gl, torch, max(10, args.steps // 4), fields, n)),
+                ("batch", lambda: batch_leg(gl, torch, max(5, args.steps // 20))),
+                ("serve", lambda: serve_leg(gl, torch)))
+        for name, fn in legs:
+            out[name] = fn()
+            progress(name)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, fields, with_amr=not args.no_extra)
+        progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
 
