@@ -359,6 +359,8 @@ def batch_leg(gl, torch, reps):
     ws = torch.empty(gl.batch_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
     args = ([i[0] for i in ins], [i[1] for i in ins], [i[2] for i in ins],
             [o[0] for o in outs], [o[1] for o in outs])
+    ms_p = _timeit(torch, lambda: gl.solve_batch(plans, *args, ws, persistent=True), reps)
+    torch.cuda.synchronize()
     ms_b = _timeit(torch, lambda: gl.solve_batch(plans, *args, ws), reps)
     torch.cuda.synchronize()
     # achieved error of every disk of the batch at seeded targets
@@ -394,11 +396,40 @@ def batch_leg(gl, torch, reps):
     cells = int(sum(d[0] ** 2 for d in disks))
     two_pass = 124 * cells   # FP32 two-pass byte model, per leaf
     return {"workload": "64 disks, n in {64..1024}, exponential/Kuzmin spirals, FP32",
-            "cells": cells, "ms_batch": ms_b, "ms_sequential": ms_s, "ms_sequential_f64": ms_64,
+            "cells": cells, "ms_batch": ms_b, "ms_batch_persistent": ms_p,
+            "forces_per_s_batch_persistent": cells / (ms_p * 1e-3),
+            "ms_sequential": ms_s, "ms_sequential_f64": ms_64,
             "forces_per_s_batch": cells / (ms_b * 1e-3), "forces_per_s_sequential": cells / (ms_s * 1e-3),
             "forces_per_s_sequential_f64": cells / (ms_64 * 1e-3),
             "roofline_two_pass": {"bytes": two_pass, "frac": two_pass / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "accuracy": acc}
+
+
+def small_batch_leg(gl, torch, reps):
+    """Many small disks (256 disks, n in {64, 128, 256}, FP32), where launch
+    gaps dominate: grouped launches, one persistent launch, one by one."""
+    import diskgen
+    disks = diskgen.batch_disks(1, count=256, sizes=(64, 128, 256))
+    plans = [gl.Plan(n, gl.F32) for (n, _, _, _) in disks]
+    ins = [[torch.from_numpy(a.ravel()).to("cuda", torch.float32) for a in d[1:]] for d in disks]
+    outs = [(torch.empty_like(i[0]), torch.empty_like(i[0])) for i in ins]
+    ws = torch.empty(gl.batch_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    args = ([i[0] for i in ins], [i[1] for i in ins], [i[2] for i in ins],
+            [o[0] for o in outs], [o[1] for o in outs])
+    ms_p = _timeit(torch, lambda: gl.solve_batch(plans, *args, ws, persistent=True), reps)
+    ms_b = _timeit(torch, lambda: gl.solve_batch(plans, *args, ws), reps)
+    ws1 = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device="cuda")
+
+    def seq():
+        for p, i, o in zip(plans, ins, outs):
+            p.solve(*i, fx=o[0], fy=o[1], workspace=ws1)
+    ms_s = _timeit(torch, seq, reps)
+    cells = int(sum(d[0] ** 2 for d in disks))
+    return {"workload": "256 disks, n in {64, 128, 256}, exponential/Kuzmin spirals, FP32", "cells": cells,
+            "ms_batch": ms_b, "ms_batch_persistent": ms_p, "ms_sequential": ms_s,
+            "forces_per_s_batch": cells / (ms_b * 1e-3),
+            "forces_per_s_batch_persistent": cells / (ms_p * 1e-3),
+            "forces_per_s_sequential": cells / (ms_s * 1e-3)}
 
 
 def serve_leg(gl, torch, nreq=2000, warm=200, rhos=(0.5, 0.8), budget=8 << 30):
@@ -730,6 +761,7 @@ def main():
                 ("nested", lambda: nested_leg(gl, torch, max(5, args.steps // 20))),
                 ("offplane", lambda: offplane_leg(gl, torch, max(10, args.steps // 4), fields, n)),
                 ("batch", lambda: batch_leg(gl, torch, max(5, args.steps // 20))),
+                ("batch_small", lambda: small_batch_leg(gl, torch, max(5, args.steps // 20))),
                 ("serve", lambda: serve_leg(gl, torch)))
         for name, fn in legs:
             out[name] = fn()

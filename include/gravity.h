@@ -224,6 +224,28 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans,
                                      void *const *fy, void *workspace, void *stream);
 
 /*
+ * As gravity_solve_batch, but the uniform midplane solves with slopes and
+ * 64 <= n0 <= 1024 (FFT sizes 128 to 2048) run in ONE persistent launch per
+ * precision, whatever their sizes: a device work queue of units (row groups,
+ * columns) in pass order, taken by resident blocks from an atomic counter;
+ * a unit waits, with a bounded spin, until its own solve's previous pass is
+ * complete (the units it waits for were taken earlier by running blocks, so
+ * every wait ends).  The other solves of the batch run as in
+ * gravity_solve_batch.  The persistent kernels use fixed transform shapes
+ * (4 elements per thread; 8 in 2048-point columns) instead of the plans'
+ * tuned variants, so results agree with gravity_solve to rounding rather
+ * than bit for bit.  Per-solve argument blocks are uploaded through a
+ * pinned staging buffer with an asynchronous copy on `stream`, so the call
+ * is not meant for graph capture.
+ * workspace: gravity_batch_workspace_bytes bytes (the same as for
+ * gravity_solve_batch; it includes the launch's tables).
+ */
+gravity_status_t gravity_solve_batch_persistent(int32_t n, const gravity_plan_t *plans,
+                                                const void *const *sigma, const void *const *dsx,
+                                                const void *const *dsy, void *const *fx,
+                                                void *const *fy, void *workspace, void *stream);
+
+/*
  * As gravity_solve_batch, for batches that include off-plane plans:
  * fz holds n device pointers (entries of midplane plans are ignored and
  * may be NULL).  Results are bit-identical to the single-solve calls.

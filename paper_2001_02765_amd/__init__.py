@@ -30,6 +30,7 @@ _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5
 # exported symbols of include/gravity.h
 SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
            "gravity_solve", "gravity_solve_noalloc", "gravity_solve_xyz", "gravity_batch_workspace_bytes", "gravity_solve_batch",
+           "gravity_solve_batch_persistent",
            "gravity_solve_batch_xyz", "gravity_solve_profiled", "gravity_stage_name",
            "gravity_server_create", "gravity_server_submit", "gravity_server_submit_xyz",
            "gravity_server_poll", "gravity_server_wait",
@@ -76,6 +77,8 @@ _lib.gravity_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(_v
 _lib.gravity_batch_workspace_bytes.restype = ctypes.c_int
 _lib.gravity_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 5 + [_vp, _vp]
 _lib.gravity_solve_batch.restype = ctypes.c_int
+_lib.gravity_solve_batch_persistent.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 5 + [_vp, _vp]
+_lib.gravity_solve_batch_persistent.restype = ctypes.c_int
 _lib.gravity_solve_batch_xyz.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 6 + [_vp, _vp]
 _lib.gravity_solve_batch_xyz.restype = ctypes.c_int
 _lib.gravity_solve_profiled.argtypes = [_vp] * 8 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -323,9 +326,11 @@ def batch_workspace_bytes(plans):
     return int(b.value)
 
 
-def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None, fz=None):
+def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None, fz=None, persistent=False):
     """Queue independent solves as one batch (see gravity_solve_batch); fz:
-    third outputs, needed when the batch holds off-plane plans."""
+    third outputs, needed when the batch holds off-plane plans.
+    persistent: gravity_solve_batch_persistent (one persistent launch per
+    precision for the uniform solves of FFT sizes 128..2048)."""
     n = len(plans)
 
     def arr(ts):
@@ -342,7 +347,12 @@ def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None, fz=None)
                              "%s[%d]" % (name, k), required=(name != "fz"))
     _check_workspace(workspace, batch_workspace_bytes(plans))
     ph = (_vp * max(1, n))(*[p.handle for p in plans])
-    if fz is None:
+    if persistent:
+        if fz is not None:
+            raise ValueError("the persistent batch takes midplane plans only")
+        _check(_lib.gravity_solve_batch_persistent(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx),
+                                                   arr(fy), _ptr(workspace), _stream_handle(stream)))
+    elif fz is None:
         _check(_lib.gravity_solve_batch(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
                                         _ptr(workspace), _stream_handle(stream)))
     else:

@@ -13,7 +13,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["kernels_f32_col.hip", "kernels_f64_col.hip", "kernels_f32_row.hip", "kernels_f64_row.hip",
-           "kernels_aux.hip", "gravity.cpp"]
+           "kernels_aux.hip", "kernels_batch.hip", "gravity.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

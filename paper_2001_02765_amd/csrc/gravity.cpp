@@ -1289,6 +1289,133 @@ gravity_status_t gravity_solve_noalloc(gravity_plan_t p, const void *sigma, cons
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Persistent-batch tables: control block, pass-major unit offsets, per-solve
+// pass counters, argument blocks.  One table per precision follows the
+// solves' workspaces in the batch workspace.
+size_t batch_table_bytes(int n) {
+    const size_t head = (sizeof(BatchCtl) + 4 * 3 * ((size_t)n + 1) + 4 * 3 * (size_t)n + 15) / 16 * 16;
+    return align256(head + (size_t)n * sizeof(BatchItem<double>));
+}
+
+// Host staging of the tables: a ring of pinned buffers, each reused only
+// once the copy last queued from it has completed (its event).
+struct Staging {
+    std::mutex mu;
+    struct Slot {
+        void *buf = nullptr;
+        size_t bytes = 0;
+        hipEvent_t ev = nullptr;
+    };
+    Slot slot[16];
+    int next = 0;
+};
+// held until the process ends (no release at exit, when the runtime may be
+// gone already)
+Staging &g_staging = *new Staging;
+
+void stage_and_copy(const std::vector<char> &host, void *dev, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_staging.mu);
+    Staging::Slot &sl = g_staging.slot[g_staging.next];
+    g_staging.next = (g_staging.next + 1) % 16;
+    if (sl.ev) hip_check(hipEventSynchronize(sl.ev), "hipEventSynchronize (staging)");
+    else hip_check(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming), "hipEventCreate");
+    if (sl.bytes < host.size()) {
+        if (sl.buf) (void)hipHostFree(sl.buf);
+        sl.buf = nullptr;
+        sl.bytes = 0;
+        hip_check(hipHostMalloc(&sl.buf, host.size(), hipHostMallocDefault), "hipHostMalloc (staging)");
+        sl.bytes = host.size();
+    }
+    std::memcpy(sl.buf, host.data(), host.size());
+    hip_check(hipMemcpyAsync(dev, sl.buf, host.size(), hipMemcpyHostToDevice, s), "batch table upload");
+    hip_check(hipEventRecord(sl.ev, s), "hipEventRecord (staging)");
+}
+
+bool persistent_ok(const gravity_plan_s &p) {
+    return !p.amr && !p.nest && p.ncomp == 2 && p.nfields == 3 && batch_size_ok(p.M);
+}
+
+// One persistent launch over the uniform solves `it` of one precision.
+template <typename T> void run_persistent(const std::vector<Item> &it, char *table, hipStream_t s) {
+    const int n = (int)it.size();
+    std::vector<uint32_t> first(3 * ((size_t)n + 1));
+    uint32_t acc = 0, ends[3];
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int r = 0; r < n; ++r) {
+            uint32_t u[3];
+            batch_units(it[r].p->M, u);
+            first[(size_t)pass * (n + 1) + r] = acc;
+            acc += u[pass];
+        }
+        first[(size_t)pass * (n + 1) + n] = acc;
+        ends[pass] = acc;
+    }
+    std::vector<BatchItem<T>> items(n);
+    for (int r = 0; r < n; ++r) {
+        const gravity_plan_s &p = *it[r].p;
+        const int nf = p.nf, H = p.M / 2;
+        const int64_t colsz = (int64_t)H * nf;
+        const T h = (T)p.h0;
+        BatchItem<T> &b = items[r];
+        std::memset((void *)&b, 0, sizeof(b));
+        b.rf.in[0] = (const T *)it[r].s;
+        b.rf.in[1] = (const T *)it[r].dx;
+        b.rf.in[2] = (const T *)it[r].dy;
+        b.rf.scale[0] = (T)1;
+        b.rf.scale[1] = h;
+        b.rf.scale[2] = h;
+        b.rf.in_pitch = nf;
+        b.rf.out = (C<T> *)(it[r].ws + p.off_a);
+        b.rf.out_pitch = nf;
+        b.rf.out_fstride = colsz;
+        b.rf.hf = h;
+        b.rf.slopes = 1;
+        b.rf.nrows = nf;
+        b.col.in = b.rf.out;
+        b.col.in_pitch = nf;
+        b.col.in_fstride = colsz;
+        b.col.q[0] = b.col.q[1] = (const T *)p.centre->q.p;
+        b.col.q_pitch = p.centre->q_pitch;
+        b.col.q_kstride = p.centre->q_kstride;
+        b.col.out = (C<T> *)(it[r].ws + p.off_b);
+        b.col.out_pitch = nf;
+        b.col.out_gstride = colsz;
+        b.col.nsub = 1;
+        b.ri.in = b.col.out;
+        b.ri.in_pitch = nf;
+        b.ri.in_gstride = colsz;
+        b.ri.out[0] = (T *)it[r].fx;
+        b.ri.out[1] = (T *)it[r].fy;
+        b.ri.out_pitch = nf;
+        b.ri.scale = (T)(p.G / ((double)p.M * (double)p.M));
+        b.ri.nrows = nf;
+        b.tw = (const C<T> *)p.tw->tw.p;
+        b.ph = (const C<T> *)p.tw->ph.p;
+        b.M = p.M;
+    }
+    const size_t o_first = sizeof(BatchCtl);
+    const size_t o_done = o_first + 4 * first.size();
+    const size_t o_items = (o_done + 4 * 3 * (size_t)n + 15) / 16 * 16;
+    std::vector<char> host(o_items + (size_t)n * sizeof(BatchItem<T>), 0);
+    BatchCtl ctl{};
+    for (int k = 0; k < 3; ++k) ctl.end[k] = ends[k];
+    std::memcpy(host.data(), &ctl, sizeof(ctl));
+    std::memcpy(host.data() + o_first, first.data(), 4 * first.size());
+    std::memcpy(host.data() + o_items, items.data(), (size_t)n * sizeof(BatchItem<T>));
+    stage_and_copy(host, table, s);
+    hip_check(launch_batch<T>((BatchCtl *)table, (const uint32_t *)(table + o_first), (uint32_t *)(table + o_done),
+                              (const BatchItem<T> *)(table + o_items), n, ends[2], s),
+              "persistent batch");
+}
+
+}  // namespace
+
+extern "C" {
+
 gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *plans, size_t *bytes) {
     return guarded([&] {
         if (n < 0 || (n > 0 && !plans) || !bytes) fail(GRAVITY_EINVAL, "bad batch arguments");
@@ -1297,7 +1424,7 @@ gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *
             if (!plans[i]) fail(GRAVITY_EINVAL, "NULL plan in batch");
             tot += align256(plans[i]->ws_bytes);
         }
-        *bytes = tot;
+        *bytes = tot + 2 * batch_table_bytes(n);  // room for the persistent launch's tables
     });
 }
 
@@ -1305,7 +1432,8 @@ gravity_status_t gravity_batch_workspace_bytes(int32_t n, const gravity_plan_t *
 // plans need theirs
 static gravity_status_t solve_batch(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
                              const void *const *dsx, const void *const *dsy, void *const *fx,
-                             void *const *fy, void *const *fz, void *workspace, void *stream) {
+                             void *const *fy, void *const *fz, void *workspace, void *stream,
+                             bool persistent = false) {
     return guarded([&] {
         if (n < 0 || (n > 0 && (!plans || !sigma || !fx || !fy))) fail(GRAVITY_EINVAL, "bad batch arguments");
         std::vector<Item> items;
@@ -1326,9 +1454,27 @@ static gravity_status_t solve_batch(int32_t n, const gravity_plan_t *plans, cons
             items.push_back(Item{plans[i], sigma[i], dx, dy, fx[i], fy[i], ws, z});
             off += align256(plans[i]->ws_bytes);
         }
-        // group solves that can share launches (stable order within a group)
         std::vector<bool> done(n, false);
         hipStream_t s = (hipStream_t)stream;
+        if (persistent) {
+            // uniform solves of the supported sizes: one launch per precision
+            char *table = (char *)workspace + off;
+            for (int prec = 0; prec < 2; ++prec) {
+                std::vector<Item> sel;
+                for (int i = 0; i < n; ++i)
+                    if (!done[i] && items[i].p->prec == prec && persistent_ok(*items[i].p)) {
+                        sel.push_back(items[i]);
+                        done[i] = true;
+                    }
+                if (sel.empty()) continue;
+                if (prec)
+                    run_persistent<double>(sel, table, s);
+                else
+                    run_persistent<float>(sel, table, s);
+                table += batch_table_bytes(n);
+            }
+        }
+        // group the other solves that can share launches (stable order within a group)
         std::vector<Item> grp;
         for (int i = 0; i < n; ++i) {
             if (done[i]) continue;
@@ -1350,6 +1496,16 @@ gravity_status_t gravity_solve_batch(int32_t n, const gravity_plan_t *plans, con
                                      const void *const *dsx, const void *const *dsy, void *const *fx,
                                      void *const *fy, void *workspace, void *stream) {
     return solve_batch(n, plans, sigma, dsx, dsy, fx, fy, nullptr, workspace, stream);
+}
+
+gravity_status_t gravity_solve_batch_persistent(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
+                                                const void *const *dsx, const void *const *dsy, void *const *fx,
+                                                void *const *fy, void *workspace, void *stream) {
+    if (!workspace && n > 0) {
+        g_err = "persistent batch needs its workspace";
+        return GRAVITY_EINVAL;
+    }
+    return solve_batch(n, plans, sigma, dsx, dsy, fx, fy, nullptr, workspace, stream, true);
 }
 
 gravity_status_t gravity_solve_batch_xyz(int32_t n, const gravity_plan_t *plans, const void *const *sigma,

@@ -157,6 +157,30 @@ template <typename T>
 hipError_t launch_nest_finalize(const double *accx, const double *accy, const uint8_t *leaf, T *fx, T *fy,
                                 int64_t n, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// one persistent launch over a batch of uniform solves of mixed sizes
+// ---------------------------------------------------------------------------
+struct BatchCtl {
+    uint32_t head;      // next unit to take (zero at launch)
+    uint32_t timeouts;  // units abandoned after a wait reached its bound
+    uint32_t end[3];    // pass boundaries: units of passes < p end at end[p]
+    uint32_t pad[3];
+};
+template <typename T> struct BatchItem {
+    RowFwdArgs<T> rf;
+    ColArgs<T> col;
+    RowInvArgs<T> ri;
+    const C<T> *tw, *ph;
+    int M;
+};
+bool batch_size_ok(int M);                 // transform sizes the persistent launch takes
+void batch_units(int M, uint32_t units[3]);  // units of each pass for one solve of size M
+// ctl, first (3 x (n+1) global unit offsets, pass-major), done (3 n counters,
+// zero at launch) and items: device memory, written before the launch
+template <typename T>
+hipError_t launch_batch(BatchCtl *ctl, const uint32_t *first, uint32_t *done, const BatchItem<T> *items, int n,
+                        uint32_t total_units, hipStream_t s);
+
 hipError_t launch_ktable(const TableArgs &a, hipStream_t s);
 // forward FFT of the columns of a table's row spectra (odd x frequencies)
 // and extraction of one real half plane, kx in [0, M/2), ky in [0, M/2]:

@@ -104,26 +104,15 @@ __device__ __forceinline__ T inject_value(const RowFwdArgs<T> &a, int f, int64_t
     return s;
 }
 
-template <typename T, int M, int V, bool PRUNED, bool INJ>
-__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
-    k_row_fwd(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
-    const RowFwdArgs<T> &a = pk.a[blockIdx.z];
-    constexpr int E = var_e(V);
-    using CF = RowCfg<T, M, E, row_scale(V)>;
-    constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
-    __shared__ C<T> lds[RPB * CF::SLOTS];
-    const int t = threadIdx.x;
-    const int r = t % RPB, tr = t / RPB;
-    const int64_t grp = xcd_row_group(blockIdx.x, gridDim.x);
-    if (grp * RPB >= a.nrows) return;  // whole block: beyond this item's rows
-    const int64_t j = grp * RPB + r;
-    const LdsAoS map{RPB, r};
+// Fields [f0, f1) of row j, transformed by the NTR lanes tr of that row; the
+// block's rows are interleaved lane by lane (map); every thread of the block
+// must call it (it contains block-wide barriers).
+template <typename T, int M, int E, bool PRUNED, bool INJ, class TW>
+__device__ __forceinline__ void row_fwd_rows(const RowFwdArgs<T> &a, int64_t j, int tr, int f0, int f1,
+                                             C<T> *lds, const LdsAoS &map, const C<T> *__restrict__ tw,
+                                             const TW &twr) {
+    constexpr int L = M / 2, NTR = L / E;
     const C<T> *__restrict__ hw = tw + M;  // exp(-i pi (2k+1)/M)
-    TwReg<T, L, NTR> twr;
-    twr.load(tw, 2, tr);
-
-    const int f0 = var_all(V) ? 0 : (int)blockIdx.y;
-    const int f1 = var_all(V) ? nfields : f0 + 1;
     for (int f = f0; f < f1; ++f) {
         const C<T> *row = INJ ? nullptr : reinterpret_cast<const C<T> *>(a.in[f] + j * a.in_pitch);
         const T sc = a.scale[f];
@@ -157,6 +146,27 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
         }
         block_sync();  // the next field's first pass reuses this row's LDS
     }
+}
+
+template <typename T, int M, int V, bool PRUNED, bool INJ>
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
+    k_row_fwd(Pack<RowFwdArgs<T>> pk, int nfields, const C<T> *__restrict__ tw) {
+    const RowFwdArgs<T> &a = pk.a[blockIdx.z];
+    constexpr int E = var_e(V);
+    using CF = RowCfg<T, M, E, row_scale(V)>;
+    constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
+    __shared__ C<T> lds[RPB * CF::SLOTS];
+    const int t = threadIdx.x;
+    const int r = t % RPB, tr = t / RPB;
+    const int64_t grp = xcd_row_group(blockIdx.x, gridDim.x);
+    if (grp * RPB >= a.nrows) return;  // whole block: beyond this item's rows
+    const int64_t j = grp * RPB + r;
+    const LdsAoS map{RPB, r};
+    TwReg<T, L, NTR> twr;
+    twr.load(tw, 2, tr);
+    const int f0 = var_all(V) ? 0 : (int)blockIdx.y;
+    const int f1 = var_all(V) ? nfields : f0 + 1;
+    row_fwd_rows<T, M, E, PRUNED, INJ>(a, j, tr, f0, f1, lds, map, tw, twr);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,14 +240,13 @@ template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col
     else return M >= 2 * col_e(V) && ColLds<T, M, V, NF, NFAM, NC>::N * (int)sizeof(C<T>) <= 163840;
 }
 
+// Column kx by the NT = M/E threads t of one group; lds: the group's
+// exchange regions (ColLds elements); every thread of the block must call it.
 template <typename T, int M, int V, int NF, int NFAM, int NC>
 __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
-                                         const C<T> *__restrict__ ph) {
+                                         const C<T> *__restrict__ ph, C<T> *lds, int t, int kx) {
     constexpr int E = col_e(V), NT = M / E, H = M / 2;
     const ColMap<M> map{col_region<M>()};
-    __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
-    const int t = threadIdx.x;
-    const int kx = blockIdx.x;
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
 
@@ -368,10 +377,12 @@ __global__ void __launch_bounds__((M / col_e(V)))
     if ((int)blockIdx.y >= a.nsub) return;  // whole block: beyond this item's sub-items
     a.in += (int64_t)blockIdx.y * a.sub_off;
     a.out += (int64_t)blockIdx.y * a.sub_off;
-    if constexpr (var_dbl(V))
+    if constexpr (var_dbl(V)) {
         col2_body<T, M, V, NF, NFAM, NC>(a, tw, ph);
-    else
-        col_body<T, M, V, NF, NFAM, NC>(a, tw, ph);
+    } else {
+        __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
+        col_body<T, M, V, NF, NFAM, NC>(a, tw, ph, lds, (int)threadIdx.x, (int)blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -381,26 +392,13 @@ __global__ void __launch_bounds__((M / col_e(V)))
 // Z[k] = (Y[k] + conj Yn) + i exp(+i pi (2k+1)/M) (Y[k] - conj Yn),
 // z = IFFT_L(Z) (unnormalised), y[2m] + i y[2m+1] = z[m] exp(+2 pi i m/M).
 // ---------------------------------------------------------------------------
-template <typename T, int M, int V>
-__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
-    k_row_inv(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
-    const RowInvArgs<T> &a = pk.a[blockIdx.z];
-    constexpr int E = var_e(V);
-    using CF = RowCfg<T, M, E, row_scale(V)>;
-    constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
-    __shared__ C<T> lds[RPB * CF::SLOTS];
-    const int t = threadIdx.x;
-    const int r = t % RPB, tr = t / RPB;
-    const int64_t grp = xcd_row_group(blockIdx.x, gridDim.x);
-    if (grp * RPB >= a.nrows) return;  // whole block: beyond this item's rows
-    const int64_t j = grp * RPB + r;
-    const LdsAoS map{RPB, r};
+// Outputs [g0, g1) of row j (see row_fwd_rows).
+template <typename T, int M, int E, class TW>
+__device__ __forceinline__ void row_inv_rows(const RowInvArgs<T> &a, int64_t j, int tr, int g0, int g1,
+                                             C<T> *lds, const LdsAoS &map, const C<T> *__restrict__ tw,
+                                             const TW &twr) {
+    constexpr int L = M / 2, NTR = L / E;
     const C<T> *__restrict__ hw = tw + M;  // exp(-i pi (2k+1)/M)
-    TwReg<T, L, NTR> twr;
-    twr.load(tw, 2, tr);
-
-    const int g0 = var_all(V) ? 0 : (int)blockIdx.y;
-    const int g1 = var_all(V) ? nout : g0 + 1;
     for (int g = g0; g < g1; ++g) {
         const C<T> *src = a.in + g * a.in_gstride + j;
 #pragma unroll
@@ -431,6 +429,27 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
         }
         block_sync();  // the next output's staging reuses this row's LDS
     }
+}
+
+template <typename T, int M, int V>
+__global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
+    k_row_inv(Pack<RowInvArgs<T>> pk, int nout, const C<T> *__restrict__ tw) {
+    const RowInvArgs<T> &a = pk.a[blockIdx.z];
+    constexpr int E = var_e(V);
+    using CF = RowCfg<T, M, E, row_scale(V)>;
+    constexpr int L = CF::L, NTR = CF::NTR, RPB = CF::RPB;
+    __shared__ C<T> lds[RPB * CF::SLOTS];
+    const int t = threadIdx.x;
+    const int r = t % RPB, tr = t / RPB;
+    const int64_t grp = xcd_row_group(blockIdx.x, gridDim.x);
+    if (grp * RPB >= a.nrows) return;  // whole block: beyond this item's rows
+    const int64_t j = grp * RPB + r;
+    const LdsAoS map{RPB, r};
+    TwReg<T, L, NTR> twr;
+    twr.load(tw, 2, tr);
+    const int g0 = var_all(V) ? 0 : (int)blockIdx.y;
+    const int g1 = var_all(V) ? nout : g0 + 1;
+    row_inv_rows<T, M, E>(a, j, tr, g0, g1, lds, map, tw, twr);
 }
 
 // ---------------------------------------------------------------------------
