@@ -342,11 +342,18 @@ template <int L> constexpr int aos_slots() { return L + 1 + ((L + 1) >> 3) + 1; 
 
 template <typename T, int L, int NT, int DIR, int NB, int P, int OFF, class MAP>
 __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP &map,
-                                      const TwReg<T, L, NT> &tr, int t) {
+                                      const TwReg<T, L, NT> &tr, int t_in) {
     using PI = PassInfo<L, NT, P>;
     constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
     constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
     constexpr int CNT = tw_pass_count<L, NT, P>();
+    // The lane index passes through an empty asm at every pass, so that the
+    // pass's LDS addresses are formed where they are used: otherwise the
+    // compiler computes the addresses of every pass of every transform of
+    // the kernel up front and keeps them all live (tens of registers, and
+    // spills in the largest transforms).
+    int t = t_in;
+    asm volatile("" : "+v"(t));
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + NT * b;

@@ -97,9 +97,10 @@ struct TableArgs {
 // Kernel variants of the three solve kernels (see kernels_impl.hpp): bit 1
 // selects 16 elements per thread (else 8), bit 0 all fields per thread; bits
 // 2-3 scale the rows per block of the row kernels (doubled, halved), bit 2
-// selects two columns per block in the column kernel (ids below 8).
+// selects two columns per block in the column kernel (ids below 8; ids 8-9
+// take 4 elements per thread, 10-13 cap the registers per lane).
 // Validity depends on size, precision and fields.
-constexpr int kNumVariants = 12;
+constexpr int kNumVariants = 14;
 bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam, int ncomp);
 

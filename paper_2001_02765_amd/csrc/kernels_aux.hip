@@ -436,6 +436,10 @@ template <typename T, int M, int NF, int NFAM, int NC> static bool col_ok(int va
         case 6: return col_var_ok<T, M, 6, NF, NFAM, NC>();
         case 8: return col_var_ok<T, M, 8, NF, NFAM, NC>();
         case 9: return col_var_ok<T, M, 9, NF, NFAM, NC>();
+        case 10: return col_var_ok<T, M, 10, NF, NFAM, NC>();
+        case 11: return col_var_ok<T, M, 11, NF, NFAM, NC>();
+        case 12: return col_var_ok<T, M, 12, NF, NFAM, NC>();
+        case 13: return col_var_ok<T, M, 13, NF, NFAM, NC>();
     }
     return false;
 }

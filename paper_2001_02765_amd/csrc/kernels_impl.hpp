@@ -64,8 +64,15 @@ constexpr bool var_all(int v) { return (v & 1) != 0; }
 constexpr bool var_dbl(int v) { return (v & 4) != 0; }
 constexpr int row_scale(int v) { return (v >> 2) == 1 ? 1 : ((v >> 2) == 2 ? -1 : 0); }
 // column kernel: ids 8 and 9 are ids 0 and 1 with 4 elements per thread
-// (twice the threads, fewer registers per thread: for FP64)
-constexpr int col_e(int v) { return v >= 8 ? 4 : var_e(v); }
+// (twice the threads, fewer registers per thread: for FP64); ids 10 and 11
+// are ids 0 and 1 held to 128 registers per lane (4 waves per SIMD), 12 and
+// 13 to 102 (5 waves per SIMD): the compiler otherwise spends registers
+// freely and these latency-bound kernels run at 2-3 waves per SIMD.
+constexpr int col_base(int v) { return v >= 10 ? (v & 1) : v; }
+constexpr int col_e(int v) { return (v == 8 || v == 9) ? 4 : var_e(col_base(v)); }
+constexpr bool col_all(int v) { return var_all(col_base(v)); }
+constexpr bool col_dbl(int v) { return v < 8 && var_dbl(v); }
+constexpr int col_waves(int v) { return v >= 12 ? 5 : (v >= 10 ? 4 : 1); }
 // a row variant exists if each row has at least 2 threads; the doubled and
 // halved ones only where they really change the rows per block
 template <typename T, int M, int V> constexpr bool row_var_ok() {
@@ -224,18 +231,20 @@ template <int M> using ColMap = std::conditional_t<(M <= 4096), LdsSwz, LdsSoA>;
 template <int M> constexpr int col_region() { return ColMap<M>::template region<M>(); }
 
 template <typename T, int M, int V, int NF, int NFAM, int NC> struct ColLds {
-    static constexpr int NB = var_all(V) ? cmax(NF, NC * NFAM) : 1;
+    static constexpr int NB = col_all(V) ? cmax(NF, NC * NFAM) : 1;
     static constexpr int N = NB * col_region<M>();
 };
 // a column variant exists if its transform has at least 2 threads and its
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col_var_ok() {
-    if constexpr (V >= 10 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
+    constexpr int B = col_base(V);
+    if constexpr (V >= 14 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
+    else if constexpr (V >= 10 && (M < 1024 || M > 4096 || NC == 3)) return false;  // capped: large midplane columns
     else if constexpr (M / col_e(V) > 1024) return false;  // threads per block
-    else if constexpr (NC == 3 && V > 1 && V < 8) return false;  // off-plane: one column, E <= 8
+    else if constexpr (NC == 3 && B > 1 && B < 8) return false;  // off-plane: one column, E <= 8
     else if constexpr (V >= 4 && V < 8) return M >= 2 * col_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
-    else if constexpr (NF == 1 && (V & 1)) return false;
+    else if constexpr (NF == 1 && (B & 1)) return false;
     else if constexpr (M <= 256 && V > 1) return false;
     else return M >= 2 * col_e(V) && ColLds<T, M, V, NF, NFAM, NC>::N * (int)sizeof(C<T>) <= 163840;
 }
@@ -256,7 +265,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[g][e] = mk<T>(0, 0);
 
-    if constexpr (var_all(V)) {
+    if constexpr (col_all(V)) {
         C<T> x[NF][E];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -289,7 +298,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
             for (int c = 0; c < NC; ++c) acc[NC + c][e] = cmul<T>(acc[NC + c][e], p);
         }
     }
-    if constexpr (var_all(V)) {
+    if constexpr (col_all(V)) {
         fft_multi<T, M, NT, +1, NC * NFAM>(acc, lds, map, twr, t);
     } else {
 #pragma unroll
@@ -371,13 +380,13 @@ __device__ __forceinline__ void col2_body(const ColArgs<T> &a, const C<T> *__res
 }
 
 template <typename T, int M, int V, int NF, int NFAM, int NC>
-__global__ void __launch_bounds__((M / col_e(V)))
+__global__ void __launch_bounds__((M / col_e(V))) __attribute__((amdgpu_waves_per_eu(col_waves(V))))
     k_col(Pack<ColArgs<T>> pk, const C<T> *__restrict__ tw, const C<T> *__restrict__ ph) {
     ColArgs<T> a = pk.a[blockIdx.z];
     if ((int)blockIdx.y >= a.nsub) return;  // whole block: beyond this item's sub-items
     a.in += (int64_t)blockIdx.y * a.sub_off;
     a.out += (int64_t)blockIdx.y * a.sub_off;
-    if constexpr (var_dbl(V)) {
+    if constexpr (col_dbl(V)) {
         col2_body<T, M, V, NF, NFAM, NC>(a, tw, ph);
     } else {
         __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
@@ -519,7 +528,7 @@ template <typename T, int M> struct Dispatch {
             if (nsub < 1 || nsub > 65535) return hipErrorInvalidValue;
             for (int i = 0; i < n; ++i)
                 if (a.a[i].nsub < 1 || a.a[i].nsub > nsub) return hipErrorInvalidValue;
-            const unsigned nblk = var_dbl(V) ? M / 4 : M / 2;
+            const unsigned nblk = col_dbl(V) ? M / 4 : M / 2;
             hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, nsub, n), dim3(M / col_e(V)), 0, s,
                                a, tw, ph);
             return hipGetLastError();
@@ -552,6 +561,10 @@ template <typename T, int M> struct Dispatch {
             case 6: return col_nf<6>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
             case 8: return col_nf<8>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
             case 9: return col_nf<9>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 10: return col_nf<10>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 11: return col_nf<11>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 12: return col_nf<12>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 13: return col_nf<13>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
         }
         return hipErrorInvalidValue;
     }
