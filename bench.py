@@ -141,6 +141,31 @@ def stored_traffic(kernel, n):
     return None
 
 
+def sweep_col(gl, torch, n, fields, steps):
+    """Mean launch time of every valid column-kernel variant of the FP32
+    solve at size n (GRAVITY_VARIANTS forces it; row kernels at the tuned
+    choice): {variant id: ms}."""
+    s, dx, dy, h = fields
+    t = [torch.from_numpy(a.ravel()).to("cuda", torch.float32) for a in (s, dx, dy)]
+    os.environ.pop("GRAVITY_VARIANTS", None)
+    base = gl.Plan(n, gl.F32, h0=h).variants
+    out = {}
+    for v in range(16):
+        os.environ["GRAVITY_VARIANTS"] = "%d,%d,%d" % (base[0], v, base[2])
+        try:
+            p = gl.Plan(n, gl.F32, h0=h)
+        except gl.GravityError:
+            continue
+        fx, fy = torch.empty_like(t[0]), torch.empty_like(t[0])
+        ws = p.workspace()
+        for _ in range(3):  # the first launch of a code object loads it
+            p.solve(*t, fx=fx, fy=fy, workspace=ws)
+        out[v] = p.profile(*t, fx, fy, ws, reps=steps)["col"]
+    os.environ.pop("GRAVITY_VARIANTS", None)
+    torch.cuda.synchronize()
+    return {"tuned": list(base), "col_ms": out}
+
+
 def progress(msg, _t0=[None]):
     """One line per finished leg on stderr (the JSON result stays the only
     line on stdout)."""
@@ -681,6 +706,9 @@ def main():
                     help="skip the AMR, batch and serving legs")
     ap.add_argument("--only", choices=["f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--sweep-col", action="store_true",
+                    help="instead of the benchmark, time every valid column-kernel variant of the FP32 "
+                         "headline solve (forced, row kernels at the tuned choice); profiling runs")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="instead of the solver, run --steps device copies of BYTES bytes "
                          "(reference kernel for hardware byte counters)")
@@ -706,6 +734,9 @@ def main():
 
     n = args.n
     fields = diskgen.noisy_spiral(n, 0)
+    if args.sweep_col:
+        print(json.dumps({"sweep_col": sweep_col(gl, torch, n, fields, args.steps)}), flush=True)
+        return
     if args.only:
         prec = gl.F32 if args.only == "f32" else gl.F64
         r = run_precision(gl, torch, prec, n, args.steps, args.warmup, fields, acc=False)
