@@ -224,10 +224,9 @@ __device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, co
     }
 }
 
-// Column exchanges use the swizzled map up to M = 4096 (measured faster);
-// the largest transforms, whose 1024-thread blocks are short of registers,
-// keep the padded map's cheaper addresses.
-template <int M> using ColMap = std::conditional_t<(M <= 4096), LdsSwz, LdsSoA>;
+// Column exchanges use the padded map, whose additive addresses cost one
+// lane address per butterfly group instead of address arithmetic per element.
+template <int M> using ColMap = LdsSoA;
 template <int M> constexpr int col_region() { return ColMap<M>::template region<M>(); }
 
 template <typename T, int M, int V, int NF, int NFAM, int NC> struct ColLds {
