@@ -257,6 +257,7 @@ def amr_leg(gl, torch, reps):
         r = {"ms": ms, "leaf_forces_per_s": p.n_leaves / (ms * 1e-3)}
         if amr == "exact":
             r["stages_ms"] = p.profile(*t, fx, fy, ws, reps=max(5, reps // 4))
+            r["variants"] = list(p.variants)
             r["col_roofline"] = _col_frac(p.n_finest, 4 if prec == gl.F32 else 8, r["stages_ms"]["col"], 2)
         torch.cuda.synchronize()
         r["accuracy"] = amr_accuracy(lay, (s, dx, dy), fx, fy, 24, 5,
@@ -291,6 +292,7 @@ def paper_amr_leg(gl, torch, reps):
         if amr == "exact":
             st = p.profile(*t, fx, fy, ws, reps=3)
             r["stages_ms"] = st
+            r["variants"] = list(p.variants)
             r["col_roofline"] = _col_frac(p.n_finest, 4 if prec == gl.F32 else 8, st["col"], 2)
         torch.cuda.synchronize()
         r["accuracy"] = amr_accuracy(lay, (s, dx, dy), fx, fy, 16, 6,
@@ -706,6 +708,8 @@ def main():
                     help="skip the AMR, batch and serving legs")
     ap.add_argument("--only", choices=["f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--sweep-col", action="store_true",
                     help="instead of the benchmark, time every valid column-kernel variant of the FP32 "
                          "headline solve (forced, row kernels at the tuned choice); profiling runs")
@@ -795,6 +799,8 @@ def main():
                 ("batch_small", lambda: small_batch_leg(gl, torch, max(5, args.steps // 20))),
                 ("serve", lambda: serve_leg(gl, torch)))
         for name, fn in legs:
+            if args.legs and name not in args.legs.split(","):
+                continue
             out[name] = fn()
             progress(name)
     if not args.no_cpu_baseline:

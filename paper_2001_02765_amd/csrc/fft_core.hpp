@@ -260,6 +260,11 @@ template <int L, int NT> struct PassInfo<L, NT, 0> {
 // 2048 points the smaller register footprint alone measured 10-15% faster
 // (column and row kernels of the 1024^2 solve), below 1024 it is neutral.
 template <int L> constexpr bool tw_compact() { return L >= 1024; }
+// FP64 transforms of 8192 points (1024-thread blocks: at most 128 registers
+// per lane) read each base twiddle from the table at its pass instead: even
+// the compact bases (28 registers) tipped those column kernels into
+// scratch memory.
+template <typename T, int L> constexpr bool tw_mem() { return sizeof(T) == 8 && L >= 8192; }
 
 // twiddle registers (complex) of one pass: R - 1 powers per butterfly
 // group, or the base twiddle only (compact); none for the first pass
@@ -281,8 +286,10 @@ template <typename T, int R> __device__ __forceinline__ void tw_powers(C<T> *p) 
 }
 
 template <typename T, int L, int NT> struct TwReg {
-    static constexpr int N = tw_count<L, NT, 0>() > 0 ? tw_count<L, NT, 0>() : 1;
+    static constexpr int N = (tw_count<L, NT, 0>() > 0 && !tw_mem<T, L>()) ? tw_count<L, NT, 0>() : 1;
     C<T> w[N];
+    const C<T> *tab;  // the table and its stride (tw_mem)
+    int tws;
 
     template <int P, int OFF>
     __device__ __forceinline__ void load_pass(const C<T> *__restrict__ tw, int tws, int t) {
@@ -306,8 +313,10 @@ template <typename T, int L, int NT> struct TwReg {
             load_pass<P + 1, OFF + CNT>(tw, tws, t);
         }
     }
-    __device__ __forceinline__ void load(const C<T> *__restrict__ tw, int tws, int t) {
-        load_pass<0, 0>(tw, tws, t);
+    __device__ __forceinline__ void load(const C<T> *__restrict__ tw, int stride, int t) {
+        tab = tw;
+        tws = stride;
+        if constexpr (!tw_mem<T, L>()) load_pass<0, 0>(tw, stride, t);
     }
 };
 
@@ -374,7 +383,10 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP 
         const int k = j & (NS - 1);
         C<T> pw[R];  // compact twiddles: the powers of this group's base twiddle
         if constexpr (NS > 1 && tw_compact<L>()) {
-            pw[1] = tr.w[OFF + b];
+            if constexpr (tw_mem<T, L>())
+                pw[1] = tr.tab[(k * (L / (NS * R))) * tr.tws];
+            else
+                pw[1] = tr.w[OFF + b];
             asm volatile("" : "+v"(pw[1].x), "+v"(pw[1].y));
             tw_powers<T, R>(pw);
         }

@@ -98,9 +98,10 @@ struct TableArgs {
 // selects 16 elements per thread (else 8), bit 0 all fields per thread; bits
 // 2-3 scale the rows per block of the row kernels (doubled, halved), bit 2
 // selects two columns per block in the column kernel (ids below 8; ids 8-9
-// take 4 elements per thread, 10-13 cap the registers per lane).
+// take 4 elements per thread, 10-13 cap the registers per lane, 14-15 split
+// two kernel families over blocks).
 // Validity depends on size, precision and fields.
-constexpr int kNumVariants = 14;
+constexpr int kNumVariants = 16;
 bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam, int ncomp);
 

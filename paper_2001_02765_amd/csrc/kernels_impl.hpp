@@ -67,12 +67,18 @@ constexpr int row_scale(int v) { return (v >> 2) == 1 ? 1 : ((v >> 2) == 2 ? -1 
 // (twice the threads, fewer registers per thread: for FP64); ids 10 and 11
 // are ids 0 and 1 held to 128 registers per lane (4 waves per SIMD), 12 and
 // 13 to 102 (5 waves per SIMD): the compiler otherwise spends registers
-// freely and these latency-bound kernels run at 2-3 waves per SIMD.
-constexpr int col_base(int v) { return v >= 10 ? (v & 1) : v; }
+// freely and these latency-bound kernels run at 2-3 waves per SIMD.  Ids 14
+// and 15 are ids 0 and 2 for two kernel families (AMR) with the families
+// split over blocks: each block transforms its column's fields and
+// accumulates one family, so half the accumulator planes are live (the
+// two-family kernels at 4096 and 8192 points otherwise spill to scratch
+// memory), at the price of transforming every field twice.
+constexpr bool col_split(int v) { return v == 14 || v == 15; }
+constexpr int col_base(int v) { return col_split(v) ? 2 * (v - 14) : (v >= 10 ? (v & 1) : v); }
 constexpr int col_e(int v) { return (v == 8 || v == 9) ? 4 : var_e(col_base(v)); }
 constexpr bool col_all(int v) { return var_all(col_base(v)); }
 constexpr bool col_dbl(int v) { return v < 8 && var_dbl(v); }
-constexpr int col_waves(int v) { return v >= 12 ? 5 : (v >= 10 ? 4 : 1); }
+constexpr int col_waves(int v) { return (v == 12 || v == 13) ? 5 : ((v == 10 || v == 11) ? 4 : 1); }
 // a row variant exists if each row has at least 2 threads; the doubled and
 // halved ones only where they really change the rows per block
 template <typename T, int M, int V> constexpr bool row_var_ok() {
@@ -195,14 +201,16 @@ __global__ void __launch_bounds__((RowCfg<T, M, var_e(V), row_scale(V)>::NTH))
 // field f.
 template <typename T, int M, int E, int NFAM, int NC>
 __device__ __forceinline__ void col_mac(C<T> (*acc)[E], const C<T> *x, int f, const ColArgs<T> &a,
-                                        int kx, int t) {
+                                        int kx, int t, int fam0 = 0) {
     constexpr int NT = M / E, H = M / 2;
 #pragma unroll
     for (int fam = 0; fam < NFAM; ++fam) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int kind = 3 * c + f;
-            const T *q = a.q[fam] + kind * a.q_kstride + (int64_t)kx * a.q_pitch;
+            // a select, not an index: a runtime index into the argument
+            // copy would place it in scratch memory
+            const T *q = (fam0 + fam ? a.q[1] : a.q[0]) + kind * a.q_kstride + (int64_t)kx * a.q_pitch;
             const T sg = (T)parity_y(kind);
             C<T>(&o)[E] = acc[NC * fam + c];
 #pragma unroll
@@ -238,8 +246,9 @@ template <typename T, int M, int V, int NF, int NFAM, int NC> struct ColLds {
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col_var_ok() {
     constexpr int B = col_base(V);
-    if constexpr (V >= 14 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
-    else if constexpr (V >= 10 && (M < 1024 || M > 4096 || NC == 3)) return false;  // capped: large midplane columns
+    if constexpr (V >= 16 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
+    else if constexpr (col_split(V) && (NFAM != 2 || M < 2048)) return false;  // large AMR columns
+    else if constexpr (V >= 10 && V < 14 && (M < 1024 || M > 4096 || NC == 3)) return false;  // capped: large midplane columns
     else if constexpr (M / col_e(V) > 1024) return false;  // threads per block
     else if constexpr (NC == 3 && B > 1 && B < 8) return false;  // off-plane: one column, E <= 8
     else if constexpr (V >= 4 && V < 8) return M >= 2 * col_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
@@ -250,17 +259,21 @@ template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col
 
 // Column kx by the NT = M/E threads t of one group; lds: the group's
 // exchange regions (ColLds elements); every thread of the block must call it.
+// Family-split variants accumulate family fam0 only (output planes
+// NC fam0 + c).
 template <typename T, int M, int V, int NF, int NFAM, int NC>
 __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__restrict__ tw,
-                                         const C<T> *__restrict__ ph, C<T> *lds, int t, int kx) {
+                                         const C<T> *__restrict__ ph, C<T> *lds, int t, int kx,
+                                         int fam0 = 0) {
     constexpr int E = col_e(V), NT = M / E, H = M / 2;
+    constexpr int NA = col_split(V) ? 1 : NFAM;  // families accumulated by this block
     const ColMap<M> map{col_region<M>()};
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
 
-    C<T> acc[NC * NFAM][E];
+    C<T> acc[NC * NA][E];
 #pragma unroll
-    for (int g = 0; g < NC * NFAM; ++g)
+    for (int g = 0; g < NC * NA; ++g)
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[g][e] = mk<T>(0, 0);
 
@@ -274,7 +287,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
         }
         fft_multi<T, M, NT, -1, NF>(x, lds, map, twr, t);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) col_mac<T, M, E, NFAM, NC>(acc, x[f], f, a, kx, t);
+        for (int f = 0; f < NF; ++f) col_mac<T, M, E, NA, NC>(acc, x[f], f, a, kx, t, fam0);
     } else {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -283,10 +296,11 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 #pragma unroll
             for (int e = 0; e < E; ++e) x[0][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
             fft_multi<T, M, NT, -1, 1>(x, lds, map, twr, t);
-            col_mac<T, M, E, NFAM, NC>(acc, x[0], f, a, kx, t);
+            col_mac<T, M, E, NA, NC>(acc, x[0], f, a, kx, t, fam0);
         }
     }
-    if constexpr (NFAM == 2) {
+    if (NFAM == 2 && (NA == 2 || fam0 == 1)) {  // the corner family's planes
+        constexpr int G0 = NA == 2 ? NC : 0;
         const C<T> px = ph[H + 1 + kx];  // exp(-i pi (kx + 1/2)/M)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -294,18 +308,18 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
             const C<T> py = ky <= H ? ph[ky] : cconj<T>(ph[M - ky]);
             const C<T> p = cmul<T>(px, py);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[NC + c][e] = cmul<T>(acc[NC + c][e], p);
+            for (int c = 0; c < NC; ++c) acc[G0 + c][e] = cmul<T>(acc[G0 + c][e], p);
         }
     }
     if constexpr (col_all(V)) {
-        fft_multi<T, M, NT, +1, NC * NFAM>(acc, lds, map, twr, t);
+        fft_multi<T, M, NT, +1, NC * NA>(acc, lds, map, twr, t);
     } else {
 #pragma unroll
-        for (int g = 0; g < NC * NFAM; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
+        for (int g = 0; g < NC * NA; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
     }
 #pragma unroll
-    for (int g = 0; g < NC * NFAM; ++g) {
-        C<T> *dst = a.out + g * a.out_gstride + (int64_t)kx * a.out_pitch;
+    for (int g = 0; g < NC * NA; ++g) {
+        C<T> *dst = a.out + (NC * fam0 + g) * a.out_gstride + (int64_t)kx * a.out_pitch;
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) dst[t + NT * e] = acc[g][e];
     }
@@ -387,6 +401,13 @@ __global__ void __launch_bounds__((M / col_e(V))) __attribute__((amdgpu_waves_pe
     a.out += (int64_t)blockIdx.y * a.sub_off;
     if constexpr (col_dbl(V)) {
         col2_body<T, M, V, NF, NFAM, NC>(a, tw, ph);
+    } else if constexpr (col_split(V)) {
+        // blocks b and b + 8 (same XCD, dispatched together) take the two
+        // families of one column, so the second read of its spectra is
+        // likely served from that XCD's L2
+        __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
+        const int b = (int)blockIdx.x;
+        col_body<T, M, V, NF, NFAM, NC>(a, tw, ph, lds, (int)threadIdx.x, (b >> 4) * 8 + (b & 7), (b >> 3) & 1);
     } else {
         __shared__ C<T> lds[ColLds<T, M, V, NF, NFAM, NC>::N];
         col_body<T, M, V, NF, NFAM, NC>(a, tw, ph, lds, (int)threadIdx.x, (int)blockIdx.x);
@@ -527,7 +548,7 @@ template <typename T, int M> struct Dispatch {
             if (nsub < 1 || nsub > 65535) return hipErrorInvalidValue;
             for (int i = 0; i < n; ++i)
                 if (a.a[i].nsub < 1 || a.a[i].nsub > nsub) return hipErrorInvalidValue;
-            const unsigned nblk = col_dbl(V) ? M / 4 : M / 2;
+            const unsigned nblk = col_dbl(V) ? M / 4 : (col_split(V) ? M : M / 2);
             hipLaunchKernelGGL((k_col<T, M, V, NF, NFAM, NC>), dim3(nblk, nsub, n), dim3(M / col_e(V)), 0, s,
                                a, tw, ph);
             return hipGetLastError();
@@ -564,6 +585,8 @@ template <typename T, int M> struct Dispatch {
             case 11: return col_nf<11>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
             case 12: return col_nf<12>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
             case 13: return col_nf<13>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 14: return col_nf<14>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 15: return col_nf<15>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
         }
         return hipErrorInvalidValue;
     }

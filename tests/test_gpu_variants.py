@@ -7,8 +7,9 @@ autotuned choice) and the result is compared with the oracle:
   * the whole 256^2 grid (512-point transforms);
   * 1024^2 (2048-point transforms, the benchmark's size): one full row, one
     full column (every row group of every XCD's share), and 256 random cells;
-  * a 3-level AMR layout on a 4096^2 finest lattice (8192-point transforms,
-    both kernel families): leaves sampled on every level.
+  * 3-level AMR layouts on 2048^2 and 4096^2 finest lattices (4096- and
+    8192-point transforms, both kernel families, so the family-split column
+    variants too): leaves sampled on every level.
 Both precisions; both the relative L2 over the targets and a per-element
 bound |dF_i| <= tol * max|F| are asserted.  Single-source tests pin every
 entry of both kernel families (closed form and all Gauss-Legendre orders).
@@ -24,7 +25,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-5}
-N_ROW_VARIANTS, COL_VARIANTS = 12, (0, 1, 2, 3, 4, 6, 8, 9, 10, 11, 12, 13)
+N_ROW_VARIANTS, COL_VARIANTS = 12, (0, 1, 2, 3, 4, 6, 8, 9, 10, 11, 12, 13, 14, 15)
 
 
 @pytest.fixture(scope="module")
@@ -103,13 +104,12 @@ def spiral1024():
     return n, (s, dx, dy), h, tg, (ox, oy)
 
 
-@pytest.fixture(scope="module")
-def amr4096():
-    lay = diskgen.ilr_layout(1024, 3, "d2")
+def _amr_case(n0):
+    lay = diskgen.ilr_layout(n0, 3, "d2")
     s, dx, dy = lay.sample(diskgen.d2)
     rect, cent, idx = oracle.leaves_of_composite(lay)
     size = rect[:, 1] - rect[:, 0]
-    rng = np.random.default_rng(4096)
+    rng = np.random.default_rng(4 * n0)
     sel = []
     for hv in np.unique(size):
         cand = np.nonzero(size == hv)[0]
@@ -118,6 +118,11 @@ def amr4096():
     ox, oy = oracle.direct(rect, s[idx], dx[idx], dy[idx], cent[sel])
     area = (rect[sel, 1] - rect[sel, 0]) * (rect[sel, 3] - rect[sel, 2])
     return lay, (s, dx, dy), idx[sel], area, (ox, oy)
+
+
+@pytest.fixture(scope="module")
+def amr_cases():
+    return {2048: _amr_case(512), 4096: _amr_case(1024)}
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -150,16 +155,17 @@ def test_every_variant_1024_row_column_sampled(gl, monkeypatch, spiral1024, prec
     print("1024^2 %s worst rel_l2 %.3e max_rel %.3e" % (prec, *worst))
 
 
+@pytest.mark.parametrize("nf", [2048, 4096])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_every_variant_amr_8192_point_transforms(gl, monkeypatch, amr4096, prec):
-    lay, fields, sel, area, ref = amr4096
+def test_every_variant_amr_large_transforms(gl, monkeypatch, amr_cases, prec, nf):
+    lay, fields, sel, area, ref = amr_cases[nf]
     t = [_dev(a, prec) for a in fields]
     worst = (0.0, 0.0)
 
     def make():
         return gl.Plan(lay.n0, _prec(gl, prec), nlevels=lay.nlevels, patches=lay.patches)
     for vs, p in _forced_plans(gl, monkeypatch, make):
-        assert p.fft_size == 8192
+        assert p.fft_size == 2 * nf
         fx, fy = p.solve(*t)
         torch.cuda.synchronize()
         got = (fx.double().cpu().numpy()[sel], fy.double().cpu().numpy()[sel])
@@ -167,7 +173,7 @@ def test_every_variant_amr_8192_point_transforms(gl, monkeypatch, amr4096, prec)
         assert e2 < TOL[prec] and em < TOL[prec], (vs, e2, em)
         worst = (max(worst[0], e2), max(worst[1], em))
         del p, fx, fy
-    print("AMR 4096^2 finest %s worst rel_l2 %.3e max_rel %.3e" % (prec, *worst))
+    print("AMR %d^2 finest %s worst rel_l2 %.3e max_rel %.3e" % (nf, prec, *worst))
 
 
 def _single_source_check(fx, fy, ox, oy, prec, what):
