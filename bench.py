@@ -150,7 +150,7 @@ def sweep_col(gl, torch, n, fields, steps):
     os.environ.pop("GRAVITY_VARIANTS", None)
     base = gl.Plan(n, gl.F32, h0=h).variants
     out = {}
-    for v in range(16):
+    for v in range(17):
         os.environ["GRAVITY_VARIANTS"] = "%d,%d,%d" % (base[0], v, base[2])
         try:
             p = gl.Plan(n, gl.F32, h0=h)

@@ -37,10 +37,17 @@
  *    modified kernel of Section 2 is used: ln(a + R) -> sgn(a) ln|a|, applied
  *    to both families by symmetry; v ln(u + R) -> 0 when v == 0.
  *  - Each closed form is evaluated in x87 extended precision (long double)
- *    and rounded to double: the double difference cancels about
- *    2 log10(offset) digits, which in plain double leaves far-field K^{x,x}
- *    entries with relative errors near 1e-1 at 2048-cell offsets.  All sums
- *    are double precision with Neumaier compensation per target.
+ *    and rounded to double.  The double difference of a far cell cancels
+ *    about 2 log10(d) digits (d its offset in cells), and the first-moment
+ *    kernels then subtract (x_t - x_c) K^{x,0} from I_uu, two terms of the
+ *    monopole's size, so extended precision does not remove the far-field
+ *    error, it bounds it: with S = |K^{x,0}| + |K^{y,0}|, each centre kernel
+ *    is within 1e-18 d^2 S and each first-moment kernel within
+ *    1e-14 d^2 S h of its exact value (checked against 40-digit quadrature
+ *    up to d = 6000: at d = 4096, 1.7e-11 S and 1.7e-7 S h).  Far entries
+ *    are small beside the near-field ones, so sums over a grid keep the
+ *    parity bar; single far entries are not a reference to that accuracy.
+ *    All sums are double precision with Neumaier compensation per target.
  *  - On a uniform grid the kernel of a source cell depends only on its
  *    offset from the target in cells (the convolution structure the paper
  *    relies on for uniform grids); oracle_uniform evaluates each offset's

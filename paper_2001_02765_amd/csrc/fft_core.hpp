@@ -363,9 +363,14 @@ struct LdsAoS {
 };
 template <int L> constexpr int aos_slots() { return L + 1 + ((L + 1) >> 3) + 1; }
 
-template <typename T, int L, int NT, int DIR, int NB, int P, int OFF, class MAP>
-__device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP &map,
-                                      const TwReg<T, L, NT> &tr, int t_in) {
+// PPO > 0: two exchange buffers (the second PPO elements on), taken in turn
+// by successive exchanges.  A buffer is written again only two exchanges
+// later, after the barrier of the exchange in between, which every thread
+// reaches only once it has read its elements, so the barrier after the reads
+// is not needed: one barrier per exchange instead of two.
+template <typename T, int L, int NT, int DIR, int NB, int P, int OFF, class MAP, int PPO, class TWR>
+__device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds0, const MAP &map, const TWR &tr,
+                                      int t_in) {
     using PI = PassInfo<L, NT, P>;
     constexpr int E = L / NT, R = PI::R, B = PI::B, NS = PI::NS;
     constexpr bool LAST = (P == Plan<L, NT>::npass - 1);
@@ -377,6 +382,7 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP 
     // spills in the largest transforms).
     int t = t_in;
     asm volatile("" : "+v"(t));
+    C<T> *lds = (PPO > 0 && (P & 1)) ? lds0 + PPO : lds0;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + NT * b;
@@ -433,17 +439,21 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds, const MAP 
 #pragma unroll
                 for (int e = 0; e < E; ++e) reg[i][e] = lds[map.at(i, t + NT * e)];
         }
-        block_sync();
-        mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT, MAP>(reg, lds, map, tr, t);
+        if constexpr (PPO == 0) block_sync();
+        mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT, MAP, PPO, TWR>(reg, lds0, map, tr, t);
     }
 }
 
 // NB length-L transforms in lockstep; reg[i][e] holds element t + NT e of
-// transform i on entry and exit.
-template <typename T, int L, int NT, int DIR, int NB, class MAP>
-__device__ __forceinline__ void fft_multi(C<T> (*reg)[L / NT], C<T> *lds, const MAP &map,
-                                          const TwReg<T, L, NT> &tr, int t) {
-    mpass<T, L, NT, DIR, NB, 0, 0, MAP>(reg, lds, map, tr, t);
+// transform i on entry and exit.  With two buffers (PPO > 0) successive
+// transforms continue the alternation when a transform has an even number
+// of exchanges; with an odd number a barrier on entry separates the last
+// reads of one transform from the first writes of the next.
+template <typename T, int L, int NT, int DIR, int NB, class MAP, int PPO = 0, class TWR>
+__device__ __forceinline__ void fft_multi(C<T> (*reg)[L / NT], C<T> *lds, const MAP &map, const TWR &tr,
+                                          int t) {
+    if constexpr (PPO > 0 && (Plan<L, NT>::npass - 1) % 2 == 1) block_sync();
+    mpass<T, L, NT, DIR, NB, 0, 0, MAP, PPO, TWR>(reg, lds, map, tr, t);
 }
 
 }  // namespace grav

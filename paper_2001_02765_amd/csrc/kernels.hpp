@@ -99,9 +99,9 @@ struct TableArgs {
 // 2-3 scale the rows per block of the row kernels (doubled, halved), bit 2
 // selects two columns per block in the column kernel (ids below 8; ids 8-9
 // take 4 elements per thread, 10-13 cap the registers per lane, 14-15 split
-// two kernel families over blocks).
+// two kernel families over blocks, 16 uses two exchange buffers).
 // Validity depends on size, precision and fields.
-constexpr int kNumVariants = 16;
+constexpr int kNumVariants = 17;
 bool row_variant_valid(int prec, int M, int var);
 bool col_variant_valid(int prec, int M, int var, int nfields, int nfam, int ncomp);
 

@@ -442,6 +442,7 @@ template <typename T, int M, int NF, int NFAM, int NC> static bool col_ok(int va
         case 13: return col_var_ok<T, M, 13, NF, NFAM, NC>();
         case 14: return col_var_ok<T, M, 14, NF, NFAM, NC>();
         case 15: return col_var_ok<T, M, 15, NF, NFAM, NC>();
+        case 16: return col_var_ok<T, M, 16, NF, NFAM, NC>();
     }
     return false;
 }

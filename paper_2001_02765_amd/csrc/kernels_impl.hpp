@@ -72,13 +72,17 @@ constexpr int row_scale(int v) { return (v >> 2) == 1 ? 1 : ((v >> 2) == 2 ? -1 
 // split over blocks: each block transforms its column's fields and
 // accumulates one family, so half the accumulator planes are live (the
 // two-family kernels at 4096 and 8192 points otherwise spill to scratch
-// memory), at the price of transforming every field twice.
+// memory), at the price of transforming every field twice.  Id 16 is id 10
+// with two exchange buffers (one barrier per exchange).
 constexpr bool col_split(int v) { return v == 14 || v == 15; }
-constexpr int col_base(int v) { return col_split(v) ? 2 * (v - 14) : (v >= 10 ? (v & 1) : v); }
+constexpr bool col_pp(int v) { return v == 16; }
+constexpr int col_base(int v) { return v == 15 ? 2 : ((v == 14 || v == 16) ? 0 : (v >= 10 ? (v & 1) : v)); }
 constexpr int col_e(int v) { return (v == 8 || v == 9) ? 4 : var_e(col_base(v)); }
 constexpr bool col_all(int v) { return var_all(col_base(v)); }
 constexpr bool col_dbl(int v) { return v < 8 && var_dbl(v); }
-constexpr int col_waves(int v) { return (v == 12 || v == 13) ? 5 : ((v == 10 || v == 11) ? 4 : 1); }
+constexpr int col_waves(int v) {
+    return (v == 12 || v == 13) ? 5 : ((v == 10 || v == 11 || v == 16) ? 4 : 1);
+}
 // a row variant exists if each row has at least 2 threads; the doubled and
 // halved ones only where they really change the rows per block
 template <typename T, int M, int V> constexpr bool row_var_ok() {
@@ -239,16 +243,19 @@ template <int M> constexpr int col_region() { return ColMap<M>::template region<
 
 template <typename T, int M, int V, int NF, int NFAM, int NC> struct ColLds {
     static constexpr int NB = col_all(V) ? cmax(NF, NC * NFAM) : 1;
-    static constexpr int N = NB * col_region<M>();
+    static constexpr int PPO = col_pp(V) ? NB * col_region<M>() : 0;  // second exchange buffer
+    static constexpr int N = NB * col_region<M>() * (col_pp(V) ? 2 : 1);
 };
 // a column variant exists if its transform has at least 2 threads and its
 // LDS fits the 160 KB of a gfx950 CU; plans without slopes (one field) and
 // small sizes keep only the variants that can differ in speed there
 template <typename T, int M, int V, int NF, int NFAM, int NC> constexpr bool col_var_ok() {
     constexpr int B = col_base(V);
-    if constexpr (V >= 16 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
+    if constexpr (V >= 17 || (V >= 4 && V < 8 && (V == 5 || V == 7 || M < 512))) return false;
     else if constexpr (col_split(V) && (NFAM != 2 || M < 2048)) return false;  // large AMR columns
-    else if constexpr (V >= 10 && V < 14 && (M < 1024 || M > 4096 || NC == 3)) return false;  // capped: large midplane columns
+    else if constexpr (col_pp(V) && (NFAM != 1 || NC != 2 || NF != 3 || M < 1024 || M > 4096)) return false;
+    else if constexpr (((V >= 10 && V < 14) || V == 16) && (M < 1024 || M > 4096 || NC == 3))
+        return false;  // capped: large midplane columns
     else if constexpr (M / col_e(V) > 1024) return false;  // threads per block
     else if constexpr (NC == 3 && B > 1 && B < 8) return false;  // off-plane: one column, E <= 8
     else if constexpr (V >= 4 && V < 8) return M >= 2 * col_e(V) && 2 * col_region<M>() * (int)sizeof(C<T>) <= 163840;
@@ -267,6 +274,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
                                          int fam0 = 0) {
     constexpr int E = col_e(V), NT = M / E, H = M / 2;
     constexpr int NA = col_split(V) ? 1 : NFAM;  // families accumulated by this block
+    constexpr int PPO = ColLds<T, M, V, NF, NFAM, NC>::PPO;
     const ColMap<M> map{col_region<M>()};
     TwReg<T, M, NT> twr;
     twr.load(tw, 1, t);
@@ -285,7 +293,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
 #pragma unroll
             for (int e = 0; e < E; ++e) x[f][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
         }
-        fft_multi<T, M, NT, -1, NF>(x, lds, map, twr, t);
+        fft_multi<T, M, NT, -1, NF, ColMap<M>, PPO>(x, lds, map, twr, t);
 #pragma unroll
         for (int f = 0; f < NF; ++f) col_mac<T, M, E, NA, NC>(acc, x[f], f, a, kx, t, fam0);
     } else {
@@ -295,7 +303,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
             const C<T> *src = a.in + f * a.in_fstride + (int64_t)kx * a.in_pitch;
 #pragma unroll
             for (int e = 0; e < E; ++e) x[0][e] = (e < E / 2) ? src[t + NT * e] : mk<T>(0, 0);
-            fft_multi<T, M, NT, -1, 1>(x, lds, map, twr, t);
+            fft_multi<T, M, NT, -1, 1, ColMap<M>, PPO>(x, lds, map, twr, t);
             col_mac<T, M, E, NA, NC>(acc, x[0], f, a, kx, t, fam0);
         }
     }
@@ -312,10 +320,10 @@ __device__ __forceinline__ void col_body(const ColArgs<T> &a, const C<T> *__rest
         }
     }
     if constexpr (col_all(V)) {
-        fft_multi<T, M, NT, +1, NC * NA>(acc, lds, map, twr, t);
+        fft_multi<T, M, NT, +1, NC * NA, ColMap<M>, PPO>(acc, lds, map, twr, t);
     } else {
 #pragma unroll
-        for (int g = 0; g < NC * NA; ++g) fft_multi<T, M, NT, +1, 1>(&acc[g], lds, map, twr, t);
+        for (int g = 0; g < NC * NA; ++g) fft_multi<T, M, NT, +1, 1, ColMap<M>, PPO>(&acc[g], lds, map, twr, t);
     }
 #pragma unroll
     for (int g = 0; g < NC * NA; ++g) {
@@ -587,6 +595,7 @@ template <typename T, int M> struct Dispatch {
             case 13: return col_nf<13>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
             case 14: return col_nf<14>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
             case 15: return col_nf<15>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
+            case 16: return col_nf<16>(a, n, nfields, nfam, ncomp, tw, ph, s, nsub);
         }
         return hipErrorInvalidValue;
     }

@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-5}
-N_ROW_VARIANTS, COL_VARIANTS = 12, (0, 1, 2, 3, 4, 6, 8, 9, 10, 11, 12, 13, 14, 15)
+N_ROW_VARIANTS, COL_VARIANTS = 12, (0, 1, 2, 3, 4, 6, 8, 9, 10, 11, 12, 13, 14, 15, 16)
 
 
 @pytest.fixture(scope="module")

@@ -132,6 +132,34 @@ def test_far_entries_precision_vs_30_digit_quadrature():
         assert abs(k[2] - float(ref[2])) < 5e-15
 
 
+def test_far_entry_error_bound():
+    """The stated per-entry accuracy of the oracle's kernels far from the
+    target (the double differences cancel and the first-moment kernels
+    subtract two terms of the monopole's size; the x87 extended precision
+    leaves, with d the offset in cells and S = |K^{x,0}| + |K^{y,0}|): each
+    centre kernel within 1e-18 d^2 S and each first-moment kernel within
+    1e-14 d^2 S h of the 40-digit quadrature of its integrand (measured up
+    to 6000 cells: 4e-19 and 5.4e-15).  At 4096-cell offsets that is 1.7e-11
+    and 1.7e-7 of S (h = 1); such entries are small next to the near-field
+    ones, so the sums stay far inside the 1e-12 parity bar."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    for D, k in [(1000, 7), (11, 4000), (-4095, 11), (6000, 100)]:
+        xl, xr, yd, yu = D - 0.5, D + 0.5, k - 0.5, k + 0.5
+        r3 = lambda x, y: (x * x + y * y) ** mp.mpf(1.5)
+        fs = [lambda x, y: x / r3(x, y), lambda x, y: (x - D) * x / r3(x, y),
+              lambda x, y: (y - k) * x / r3(x, y), lambda x, y: y / r3(x, y),
+              lambda x, y: (x - D) * y / r3(x, y), lambda x, y: (y - k) * y / r3(x, y)]
+        ref = [float(mp.quad(f, [xl, xr], [yd, yu])) for f in fs]
+        got = oracle.cell_kernels(0.0, 0.0, xl, xr, yd, yu)
+        d2 = float(D * D + k * k)
+        S = abs(ref[0]) + abs(ref[3])
+        for i in (0, 3):
+            assert abs(got[i] - ref[i]) <= 1e-18 * d2 * S, (D, k, i)
+        for i in (1, 2, 4, 5):
+            assert abs(got[i] - ref[i]) <= 1e-14 * d2 * S, (D, k, i)
+
+
 def _load_table(name):
     rows = [l.split() for l in open(os.path.join(GOLDEN, name)) if l.strip() and not l.startswith("#")]
     return {int(r[0]): [float(x) for x in r[1:]] for r in rows}
