@@ -287,65 +287,72 @@ __global__ void __launch_bounds__(256) k_nest_lift(const T *fx, const T *fy, dou
 // with the neighbour directions (sx, sy), (-sx, sy), (sx, -sy), (-sx, -sy)
 // in that order.  av(a, b) tells whether parent (I + a, J + b) exists.
 // Writes up to 9 (a, b, weight) and returns the count.
-struct StencilTerm {
-    int a, b;
-    double w;
-};
-template <class AV> __device__ int nest_stencil(const AV &av, int sx, int sy, StencilTerm *st) {
-    bool all = true;
-    for (int b = -1; b <= 1; ++b)
-        for (int a = -1; a <= 1; ++a) all = all && av(a, b);
-    if (all) {
-        int n = 0;
-        for (int b = -1; b <= 1; ++b) {
-            const double wy = b == 0 ? 15.0 / 16.0 : (b == sy ? 5.0 / 32.0 : -3.0 / 32.0);
-            for (int a = -1; a <= 1; ++a) {
-                const double wx = a == 0 ? 15.0 / 16.0 : (a == sx ? 5.0 / 32.0 : -3.0 / 32.0);
-                st[n++] = StencilTerm{a, b, wx * wy};
+// The far-field stencil of a cell, in coordinates turned by its parity: the
+// parent's neighbour (p sx, q sy), p, q in {-1, 0, 1}, lies towards the cell
+// for p = 1 (q = 1).  The first form whose points are all available wins:
+// biquadratic over the 3x3 block, else bilinear over a quadrant (ex, ey),
+// planar over (ex, 0) and (0, ey), linear along x or y, the parent alone.
+// Only scalars (kind, ex, ey) are kept: weights are formed per point.
+struct NestStencil {
+    int kind;  // 0 biquadratic, 1 bilinear, 2 planar, 3 linear in x, 4 linear in y, 5 parent
+    int ex, ey;
+    // weight of point (p, q), or false if the stencil does not use it
+    __device__ __forceinline__ bool weight(int p, int q, double &w) const {
+        const double al = ex / 4.0, be = ey / 4.0;
+        switch (kind) {
+            case 0: {
+                const double wx = p == 0 ? 15.0 / 16.0 : (p == 1 ? 5.0 / 32.0 : -3.0 / 32.0);
+                const double wy = q == 0 ? 15.0 / 16.0 : (q == 1 ? 5.0 / 32.0 : -3.0 / 32.0);
+                w = wx * wy;
+                return true;
             }
+            case 1:
+                if ((p != 0 && p != ex) || (q != 0 && q != ey)) return false;
+                w = (p == 0 ? 1 - al : al) * (q == 0 ? 1 - be : be);
+                return true;
+            case 2:
+                if (p == 0 && q == 0) w = 1 - al - be;
+                else if (p == ex && q == 0) w = al;
+                else if (p == 0 && q == ey) w = be;
+                else return false;
+                return true;
+            case 3:
+                if (q != 0 || (p != 0 && p != ex)) return false;
+                w = p == 0 ? 1 - al : al;
+                return true;
+            case 4:
+                if (p != 0 || (q != 0 && q != ey)) return false;
+                w = q == 0 ? 1 - be : be;
+                return true;
+            default:
+                if (p != 0 || q != 0) return false;
+                w = 1.0;
+                return true;
         }
-        return n;
     }
-    const int dxs[4] = {sx, -sx, sx, -sx}, dys[4] = {sy, sy, -sy, -sy};
+};
+template <class AV> __device__ __forceinline__ NestStencil nest_stencil(const AV &av, int sx, int sy) {
+    auto avn = [&](int p, int q) { return av(p * sx, q * sy); };
+    bool all = true;
+#pragma unroll
+    for (int q = -1; q <= 1; ++q)
+#pragma unroll
+        for (int p = -1; p <= 1; ++p) all = all && avn(p, q);
+    if (all) return NestStencil{0, 0, 0};
+    // quadrants (ex, ey) = (1, 1), (-1, 1), (1, -1), (-1, -1) in turn
     for (int d = 0; d < 4; ++d) {
-        const int ex = dxs[d], ey = dys[d];
-        if (av(ex, 0) && av(0, ey) && av(ex, ey)) {
-            const double al = sx * ex / 4.0, be = sy * ey / 4.0;
-            st[0] = StencilTerm{0, 0, (1 - al) * (1 - be)};
-            st[1] = StencilTerm{ex, 0, al * (1 - be)};
-            st[2] = StencilTerm{0, ey, (1 - al) * be};
-            st[3] = StencilTerm{ex, ey, al * be};
-            return 4;
-        }
+        const int ex = (d & 1) ? -1 : 1, ey = (d & 2) ? -1 : 1;
+        if (avn(ex, 0) && avn(0, ey) && avn(ex, ey)) return NestStencil{1, ex, ey};
     }
     for (int d = 0; d < 4; ++d) {
-        const int ex = dxs[d], ey = dys[d];
-        if (av(ex, 0) && av(0, ey)) {
-            const double al = sx * ex / 4.0, be = sy * ey / 4.0;
-            st[0] = StencilTerm{0, 0, 1 - al - be};
-            st[1] = StencilTerm{ex, 0, al};
-            st[2] = StencilTerm{0, ey, be};
-            return 3;
-        }
+        const int ex = (d & 1) ? -1 : 1, ey = (d & 2) ? -1 : 1;
+        if (avn(ex, 0) && avn(0, ey)) return NestStencil{2, ex, ey};
     }
-    for (int ex = sx, k = 0; k < 2; ++k, ex = -ex) {
-        if (av(ex, 0)) {
-            const double al = sx * ex / 4.0;
-            st[0] = StencilTerm{0, 0, 1 - al};
-            st[1] = StencilTerm{ex, 0, al};
-            return 2;
-        }
-    }
-    for (int ey = sy, k = 0; k < 2; ++k, ey = -ey) {
-        if (av(0, ey)) {
-            const double be = sy * ey / 4.0;
-            st[0] = StencilTerm{0, 0, 1 - be};
-            st[1] = StencilTerm{0, ey, be};
-            return 2;
-        }
-    }
-    st[0] = StencilTerm{0, 0, 1.0};
-    return 1;
+    if (avn(1, 0)) return NestStencil{3, 1, 0};
+    if (avn(-1, 0)) return NestStencil{3, -1, 0};
+    if (avn(0, 1)) return NestStencil{4, 0, 1};
+    if (avn(0, -1)) return NestStencil{4, 0, -1};
+    return NestStencil{5, 0, 0};
 }
 
 // One thread per cell of a box: level-l cells of the box get
@@ -369,17 +376,21 @@ template <typename T> __global__ void __launch_bounds__(256) k_nest_combine(Comb
         const int32_t q = cown[(cj + db) * kNestCoarse + ci + da];
         return (q & 0x0FFFFFFF) != a.sentinel && (q >> 28) == 0;
     };
-    StencilTerm st[9];
-    const int n = nest_stencil(av, sx, sy, st);
+    const NestStencil st = nest_stencil(av, sx, sy);
     const T *cfx = a.cfx + (int64_t)b * kNestCoarse * kNestCoarse;
     const T *cfy = a.cfy + (int64_t)b * kNestCoarse * kNestCoarse;
     double ex = 0.0, ey = 0.0;
-    for (int k = 0; k < n; ++k) {
-        const int pos = (cj + st[k].b) * kNestCoarse + ci + st[k].a;
-        const int32_t pc = cown[pos] & 0x0FFFFFFF;
-        ex += st[k].w * (a.accx[pc] - (double)cfx[pos]);
-        ey += st[k].w * (a.accy[pc] - (double)cfy[pos]);
-    }
+#pragma unroll
+    for (int q = -1; q <= 1; ++q)
+#pragma unroll
+        for (int p = -1; p <= 1; ++p) {
+            double w;
+            if (!st.weight(p, q, w)) continue;
+            const int pos = (cj + q * sy) * kNestCoarse + ci + p * sx;
+            const int32_t pc = cown[pos] & 0x0FFFFFFF;
+            ex += w * (a.accx[pc] - (double)cfx[pos]);
+            ey += w * (a.accy[pc] - (double)cfy[pos]);
+        }
     a.accx[c] = (double)a.ffx[fo] + ex;
     a.accy[c] = (double)a.ffy[fo] + ey;
 }
