@@ -321,31 +321,15 @@ template <typename T, int L, int NT> struct TwReg {
 };
 
 // LDS address maps for the exchanges of fft_multi: element x of transform i.
-// SoA: one contiguous region per transform (column kernels), in two forms.
-// LdsSwz puts element x at x ^ ((x >> 3) & 31), a permutation inside each
-// aligned block of 32 elements: it spreads the power-of-two Stockham strides
-// over the banks and keeps the contiguous reads t + NT e contiguous, but its
-// address is not additive, so every element of an exchange costs address
-// instructions.  LdsSoA pads one slot per 32 elements, LdsAoS interleaves the
-// RPB rows of a block element by element, row fastest (row kernels, whose
-// lanes are interleaved the same way; one pad slot per 8).  Both padded maps
-// are additive: at(i, b + c) = at(i, b) + off(c) when b mod BLK + c mod BLK <
-// BLK (no carry into a pad), so an exchange forms one lane address per
-// butterfly group and reaches its elements with constant offsets.
-struct LdsSwz {
-    static constexpr bool kAdditive = false;
-    static constexpr int BLK = 1;
-    int reg;
-    __device__ __forceinline__ int at(int i, int x) const { return i * reg + (x ^ ((x >> 3) & 31)); }
-    __device__ __forceinline__ int off(int c) const { return c; }
-    __device__ __forceinline__ int ioff(int i) const { return i * reg; }
-    template <int L> static constexpr int region() {
-        static_assert(L % 32 == 0, "swizzled regions hold whole blocks of 32 elements");
-        return L;
-    }
-};
+// LdsSoA: one contiguous region per transform (column kernels), one pad slot
+// per 32 elements; LdsAoS: the RPB rows of a block interleaved element by
+// element, row fastest (row kernels, whose lanes are interleaved the same
+// way), one pad slot per 8.  Both are additive: at(i, b + c) = at(i, b) +
+// off(c) when b mod BLK + c mod BLK < BLK (no carry into a pad), so an
+// exchange forms one lane address per butterfly group and reaches its
+// elements with constant offsets (an XOR swizzle spreads the banks better
+// but costs address arithmetic per element, which measured slower).
 struct LdsSoA {
-    static constexpr bool kAdditive = true;
     static constexpr int BLK = 32;
     int reg;
     __device__ __forceinline__ int at(int i, int x) const { return i * reg + x + (x >> 5); }
@@ -354,7 +338,6 @@ struct LdsSoA {
     template <int L> static constexpr int region() { return L + (L >> 5) + 1; }
 };
 struct LdsAoS {
-    static constexpr bool kAdditive = true;
     static constexpr int BLK = 8;
     int stride, lane;
     __device__ __forceinline__ int at(int, int x) const { return (x + (x >> 3)) * stride + lane; }
@@ -412,7 +395,7 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds0, const MAP
                 for (int r = 0; r < R; ++r) reg[i][b + r * B] = v[r];
             } else {
                 const int base = (j / NS) * NS * R + k;
-                if constexpr (MAP::kAdditive && NS * R >= MAP::BLK) {
+                if constexpr (NS * R >= MAP::BLK) {
                     // base mod BLK = k < NS and (r NS) mod BLK <= BLK - NS
                     C<T> *p = lds + map.at(i, base);
 #pragma unroll
@@ -426,18 +409,13 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds0, const MAP
     }
     if constexpr (!LAST) {
         block_sync();
-        if constexpr (MAP::kAdditive) {
+        {
             // NT and BLK are powers of two: t mod BLK + (NT e) mod BLK < BLK
             const C<T> *p = lds + map.at(0, t);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int e = 0; e < E; ++e) reg[i][e] = p[map.ioff(i) + map.off(NT * e)];
-        } else {
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-#pragma unroll
-                for (int e = 0; e < E; ++e) reg[i][e] = lds[map.at(i, t + NT * e)];
         }
         if constexpr (PPO == 0) block_sync();
         mpass<T, L, NT, DIR, NB, P + 1, OFF + CNT, MAP, PPO, TWR>(reg, lds0, map, tr, t);
