@@ -68,6 +68,20 @@ void *dev_alloc(size_t bytes, const char *what) {
     return p;
 }
 
+// Teardown (frees, the server's streams and events) can run while the
+// caller captures a stream into a graph: a plan dropped by a garbage
+// collector in the middle of a capture, for instance.  Under the default
+// (global) capture mode such calls are prohibited during any capture and
+// would invalidate it; they touch no captured work, so they run with this
+// thread's capture mode relaxed.
+struct RelaxedCapture {
+    hipStreamCaptureMode prev = hipStreamCaptureModeRelaxed;
+    RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+    ~RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+    RelaxedCapture(const RelaxedCapture &) = delete;
+    RelaxedCapture &operator=(const RelaxedCapture &) = delete;
+};
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -75,7 +89,10 @@ struct DevBuf {
     DevBuf(size_t b, const char *what) : p(dev_alloc(b, what)), bytes(b) {}
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            RelaxedCapture relaxed;
+            (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -1913,6 +1930,7 @@ void gravity_server_destroy(gravity_server_t srv) {
     }
     srv->cv_work.notify_all();
     if (srv->th.joinable()) srv->th.join();
+    RelaxedCapture relaxed;
     for (auto s : srv->streams) (void)hipStreamDestroy(s);
     for (auto e : srv->event_pool)
         if (e) (void)hipEventDestroy(e);

@@ -663,6 +663,37 @@ def test_solve_replays_from_a_hip_graph(gl):
         torch.cuda.synchronize()
 
 
+def test_plan_released_during_a_capture(gl):
+    """A plan released while the caller captures a graph (a garbage collector
+    may drop one at any point) frees its device memory without invalidating
+    the capture; the captured solve replays bit for bit."""
+    n = 128
+    s, dx, dy, h = diskgen.noisy_spiral(n, 4)
+    plan = gl.Plan(n, gl.F32, h0=h)
+    t = [torch.from_numpy(np.ascontiguousarray(v).ravel()).to("cuda", torch.float32) for v in (s, dx, dy)]
+    out = (torch.empty(n * n, device="cuda"), torch.empty(n * n, device="cuda"))
+    ws = plan.workspace()
+    # a cell size no other plan uses: its kernel spectra are its own, freed
+    # when it goes
+    doomed = gl.Plan(64, gl.F64, h0=2.0 / 64 * 1.2345)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan.solve(*t, fx=out[0], fy=out[1], workspace=ws, stream=st)
+    torch.cuda.synchronize()
+    ref = (out[0].clone(), out[1].clone())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        plan.solve(*t, fx=out[0], fy=out[1], workspace=ws, stream=st)
+        doomed.close()
+    for rep in range(2):
+        out[0].fill_(0.0)
+        out[1].fill_(0.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), rep
+
+
 def test_server_waits_for_the_callers_stream(gl):
     """Inputs still being written on the caller's stream when the request is
     submitted: the server's work waits for that stream (an event recorded at
