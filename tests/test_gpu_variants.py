@@ -176,6 +176,55 @@ def test_every_variant_amr_large_transforms(gl, monkeypatch, amr_cases, prec, nf
     print("AMR %d^2 finest %s worst rel_l2 %.3e max_rel %.3e" % (nf, prec, *worst))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_column_variant_offplane_amr(gl, monkeypatch, prec):
+    """Targets at a height above a 3-level AMR layout on a 2048^2 finest
+    lattice (4096-point transforms, both kernel families, three force
+    components): every valid column variant, the family-split ones
+    included, against the off-plane leaf sum on sampled leaves of every
+    level."""
+    lay = diskgen.ilr_layout(512, 3, "d2")
+    s, dx, dy = lay.sample(diskgen.d2)
+    rect, cent, idx = oracle.leaves_of_composite(lay)
+    size = rect[:, 1] - rect[:, 0]
+    rng = np.random.default_rng(2048)
+    sel = []
+    for hv in np.unique(size):
+        cand = np.nonzero(size == hv)[0]
+        sel.extend(rng.choice(cand, min(12, len(cand)), replace=False))
+    sel = np.array(sorted(sel))
+    z = 0.05
+    ref = oracle.direct_z(rect, s[idx], dx[idx], dy[idx], cent[sel], z)
+    area = (rect[sel, 1] - rect[sel, 0]) ** 2
+    t = [_dev(a, prec) for a in (s, dx, dy)]
+
+    def make():
+        return gl.Plan(lay.n0, _prec(gl, prec), nlevels=lay.nlevels, patches=lay.patches, z=z)
+    monkeypatch.delenv("GRAVITY_VARIANTS", raising=False)
+    base = make().variants
+    n_ok, worst = 0, (0.0, 0.0)
+    for v in COL_VARIANTS:
+        monkeypatch.setenv("GRAVITY_VARIANTS", "%d,%d,%d" % (base[0], v, base[2]))
+        try:
+            p = make()
+        except gl.GravityError as e:
+            assert e.status == gl.EINVAL, e
+            continue
+        assert p.fft_size == 4096
+        n_ok += 1
+        f = p.solve_xyz(*t)
+        torch.cuda.synchronize()
+        got = [c.double().cpu().numpy()[idx[sel]] for c in f]
+        e2, em = an.rel_l2(got, ref, area), max_rel(got, ref)
+        assert e2 < TOL[prec] and em < TOL[prec], (v, e2, em)
+        worst = (max(worst[0], e2), max(worst[1], em))
+        del p, f
+    monkeypatch.delenv("GRAVITY_VARIANTS")
+    assert n_ok >= 3
+    print("off-plane AMR 2048^2 finest %s: %d column variants, worst rel_l2 %.3e max_rel %.3e"
+          % (prec, n_ok, *worst))
+
+
 def _single_source_check(fx, fy, ox, oy, prec, what):
     e2 = an.rel_l2((fx, fy), (ox, oy))
     em = max_rel((fx, fy), (ox, oy))
