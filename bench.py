@@ -9,10 +9,11 @@ latency, the per-stage roofline of the dominant kernel, the whole-solve
 roofline under the compulsory and two-pass byte models, the spread over the
 disks of seeds 0-4, the 2048^2-cell reading of the headline size, the exact
 and nested-correction AMR workloads, the off-plane, batched and served
-workloads (each beside the plain FP64 path), the achieved error of every
-result against the FP64 oracle (relative L2 and max|dF|/max|F| on seeded
-target samples) and the CPU oracle's rate on bounded samples are reported on
-the same JSON line.
+workloads (each beside the plain FP64 path), the same convolution through
+the vendor FFT library (torch.fft, a timing comparator outside the product
+path), the achieved error of every result against the FP64 oracle (relative
+L2 and max|dF|/max|F| on seeded target samples) and the CPU oracle's rate on
+bounded samples are reported on the same JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -650,6 +651,50 @@ def cpu_baseline_amr(threads, budget_s):
                       "each summed over all %d leaves, %.1f s" % (k, per, len(levels), len(idx), el)}
 
 
+def library_fft_leg(gl, torch, n, reps, ours):
+    """Timing comparator outside the product path: the same zero-padded
+    convolution written with the vendor FFT library through torch.fft
+    (rocFFT): the three fields padded to (2n)^2, real-to-complex 2D
+    transforms, the six spectral products, complex-to-real inverses of the
+    two components, the n x n corner kept.  The spectra are random tensors
+    of the right shape (only the time is compared; the library path is not
+    part of the solve).  ours: {"f32": ms, "f64": ms} of the library's own
+    solve at the same size."""
+    m = 2 * n
+    out = {"workload": "uniform %dx%d cells, zero-padded %d^2 FFT, torch.fft (rocFFT) rfft2 of 3 fields, "
+                       "6 spectral products, irfft2 of 2 components" % (n, n, m)}
+    g = torch.Generator(device="cuda").manual_seed(0)
+    for name, dt, cdt in (("f32", torch.float32, torch.complex64), ("f64", torch.float64, torch.complex128)):
+        src = torch.rand((3, n, n), dtype=dt, device="cuda", generator=g)
+        kr = torch.rand((6, m, m // 2 + 1), dtype=dt, device="cuda", generator=g)
+        ki = torch.rand((6, m, m // 2 + 1), dtype=dt, device="cuda", generator=g)
+        kern = torch.complex(kr, ki).to(cdt)
+        pad = torch.zeros((3, m, m), dtype=dt, device="cuda")
+        res = torch.empty((2, n, n), dtype=dt, device="cuda")
+
+        def solve():
+            pad[:, :n, :n] = src
+            X = torch.fft.rfft2(pad)
+            fx = X[0] * kern[0] + X[1] * kern[1] + X[2] * kern[2]
+            fy = X[0] * kern[3] + X[1] * kern[4] + X[2] * kern[5]
+            res[0] = torch.fft.irfft2(fx, s=(m, m))[:n, :n]
+            res[1] = torch.fft.irfft2(fy, s=(m, m))[:n, :n]
+        ms = _timeit(torch, solve, reps)
+        X = torch.fft.rfft2(pad)
+
+        def transforms():  # the library's transforms alone (no padding, no products)
+            torch.fft.rfft2(pad)
+            torch.fft.irfft2(X[0], s=(m, m))
+            torch.fft.irfft2(X[1], s=(m, m))
+        ms_fft = _timeit(torch, transforms, reps)
+        out[name] = {"ms": ms, "forces_per_s": n * n / (ms * 1e-3), "transforms_only_ms": ms_fft,
+                     "ours_ms": ours[name], "speedup_of_ours": ms / ours[name]}
+        del X
+        del src, kr, ki, kern, pad, res
+    torch.cuda.synchronize()
+    return out
+
+
 def seed_spread(gl, torch, n, steps, warmup, first):
     """FP32 forces/s of the headline solve on the disks of seeds 0-4 (seed 0
     is the main run): median and spread."""
@@ -790,6 +835,8 @@ def main():
     if not args.no_extra:
         legs = (("seed_spread", lambda: seed_spread(gl, torch, n, max(20, args.steps // 2), args.warmup,
                                                     r32["value"])),
+                ("library_fft", lambda: library_fft_leg(gl, torch, n, max(20, args.steps // 4),
+                                                        {"f32": r32["ms_per_step"], "f64": r64["ms_per_step"]})),
                 ("n2048", lambda: n2048_leg(gl, torch, max(10, args.steps // 4), 5)),
                 ("amr", lambda: amr_leg(gl, torch, max(10, args.steps // 4))),
                 ("paper_amr", lambda: paper_amr_leg(gl, torch, max(5, args.steps // 20))),
