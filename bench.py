@@ -142,29 +142,37 @@ def stored_traffic(kernel, n):
     return None
 
 
-def sweep_col(gl, torch, n, fields, steps):
-    """Mean launch time of every valid column-kernel variant of the FP32
-    solve at size n (GRAVITY_VARIANTS forces it; row kernels at the tuned
-    choice): {variant id: ms}."""
+def sweep_variants(gl, torch, n, fields, steps, stages=("row_fwd", "col", "row_inv")):
+    """Mean launch time of every valid variant of each solve kernel in
+    stages of the FP32 solve at size n, one kernel at a time
+    (GRAVITY_VARIANTS forces it; the other two at the tuned choice):
+    {"tuned": ids, "row_fwd_ms": {id: ms}, "col_ms": {...}, "row_inv_ms": {...}}."""
     s, dx, dy, h = fields
     t = [torch.from_numpy(a.ravel()).to("cuda", torch.float32) for a in (s, dx, dy)]
     os.environ.pop("GRAVITY_VARIANTS", None)
     base = gl.Plan(n, gl.F32, h0=h).variants
-    out = {}
-    for v in range(17):
-        os.environ["GRAVITY_VARIANTS"] = "%d,%d,%d" % (base[0], v, base[2])
-        try:
-            p = gl.Plan(n, gl.F32, h0=h)
-        except gl.GravityError:
+    out = {"tuned": list(base)}
+    for pos, stage in ((0, "row_fwd"), (1, "col"), (2, "row_inv")):
+        if stage not in stages:
             continue
-        fx, fy = torch.empty_like(t[0]), torch.empty_like(t[0])
-        ws = p.workspace()
-        for _ in range(3):  # the first launch of a code object loads it
-            p.solve(*t, fx=fx, fy=fy, workspace=ws)
-        out[v] = p.profile(*t, fx, fy, ws, reps=steps)["col"]
+        res = {}
+        for v in range(17):
+            ids = list(base)
+            ids[pos] = v
+            os.environ["GRAVITY_VARIANTS"] = "%d,%d,%d" % tuple(ids)
+            try:
+                p = gl.Plan(n, gl.F32, h0=h)
+            except gl.GravityError:
+                continue
+            fx, fy = torch.empty_like(t[0]), torch.empty_like(t[0])
+            ws = p.workspace()
+            for _ in range(3):  # the first launch of a code object loads it
+                p.solve(*t, fx=fx, fy=fy, workspace=ws)
+            res[v] = p.profile(*t, fx, fy, ws, reps=steps)[stage]
+        out[stage + "_ms"] = res
     os.environ.pop("GRAVITY_VARIANTS", None)
     torch.cuda.synchronize()
-    return {"tuned": list(base), "col_ms": out}
+    return out
 
 
 def progress(msg, _t0=[None]):
@@ -756,8 +764,11 @@ def main():
     ap.add_argument("--legs", default="",
                     help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--sweep-col", action="store_true",
-                    help="instead of the benchmark, time every valid column-kernel variant of the FP32 "
-                         "headline solve (forced, row kernels at the tuned choice); profiling runs")
+                    help="as --sweep, the column kernel only")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark, time every valid variant of each kernel of the FP32 "
+                         "headline solve (forced one kernel at a time, the others at the tuned choice); "
+                         "profiling runs")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="instead of the solver, run --steps device copies of BYTES bytes "
                          "(reference kernel for hardware byte counters)")
@@ -783,8 +794,11 @@ def main():
 
     n = args.n
     fields = diskgen.noisy_spiral(n, 0)
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_variants(gl, torch, n, fields, args.steps)}), flush=True)
+        return
     if args.sweep_col:
-        print(json.dumps({"sweep_col": sweep_col(gl, torch, n, fields, args.steps)}), flush=True)
+        print(json.dumps({"sweep_col": sweep_variants(gl, torch, n, fields, args.steps, ("col",))}), flush=True)
         return
     if args.only:
         prec = gl.F32 if args.only == "f32" else gl.F64
