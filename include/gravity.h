@@ -246,6 +246,20 @@ gravity_status_t gravity_solve_batch_persistent(int32_t n, const gravity_plan_t 
                                                 void *const *fy, void *workspace, void *stream);
 
 /*
+ * Diagnostics of the last gravity_solve_batch_persistent call made with
+ * these n plans and this workspace: waits for `stream` (the call's stream)
+ * and stores in *abandoned the number of work units whose bounded wait
+ * reached its limit, so that the unit and the rest of its block's work were
+ * skipped and those solves' results are incomplete.  The queue's ordering
+ * excludes this (every awaited unit is held by a running block); a non-zero
+ * count reports a device or library fault.  Host-synchronising; for tests
+ * and monitoring, not for the solve path.
+ */
+gravity_status_t gravity_batch_persistent_abandoned(int32_t n, const gravity_plan_t *plans,
+                                                   const void *workspace, void *stream,
+                                                   uint32_t *abandoned);
+
+/*
  * As gravity_solve_batch, for batches that include off-plane plans:
  * fz holds n device pointers (entries of midplane plans are ignored and
  * may be NULL).  Results are bit-identical to the single-solve calls.

@@ -30,7 +30,7 @@ _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5
 # exported symbols of include/gravity.h
 SYMBOLS = ("gravity_plan", "gravity_plan_workspace_bytes", "gravity_plan_get_info",
            "gravity_solve", "gravity_solve_noalloc", "gravity_solve_xyz", "gravity_batch_workspace_bytes", "gravity_solve_batch",
-           "gravity_solve_batch_persistent",
+           "gravity_solve_batch_persistent", "gravity_batch_persistent_abandoned",
            "gravity_solve_batch_xyz", "gravity_solve_profiled", "gravity_stage_name",
            "gravity_server_create", "gravity_server_submit", "gravity_server_submit_xyz",
            "gravity_server_poll", "gravity_server_wait",
@@ -79,6 +79,9 @@ _lib.gravity_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [cty
 _lib.gravity_solve_batch.restype = ctypes.c_int
 _lib.gravity_solve_batch_persistent.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 5 + [_vp, _vp]
 _lib.gravity_solve_batch_persistent.restype = ctypes.c_int
+_lib.gravity_batch_persistent_abandoned.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp), _vp, _vp,
+                                                    ctypes.POINTER(ctypes.c_uint32)]
+_lib.gravity_batch_persistent_abandoned.restype = ctypes.c_int
 _lib.gravity_solve_batch_xyz.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)] + [ctypes.POINTER(_vp)] * 6 + [_vp, _vp]
 _lib.gravity_solve_batch_xyz.restype = ctypes.c_int
 _lib.gravity_solve_profiled.argtypes = [_vp] * 8 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -358,6 +361,18 @@ def solve_batch(plans, sigma, dsx, dsy, fx, fy, workspace, stream=None, fz=None,
     else:
         _check(_lib.gravity_solve_batch_xyz(n, ph, arr(sigma), arr(dsx), arr(dsy), arr(fx), arr(fy),
                                             arr(fz), _ptr(workspace), _stream_handle(stream)))
+
+
+def batch_persistent_abandoned(plans, workspace, stream=None):
+    """Work units the last persistent batch over these plans and this
+    workspace abandoned at a wait's bound (0 unless the device or the
+    library is at fault); waits for the stream."""
+    n = len(plans)
+    ph = (_vp * max(1, n))(*[p.handle for p in plans])
+    out = ctypes.c_uint32(0)
+    _check(_lib.gravity_batch_persistent_abandoned(n, ph, _ptr(workspace), _stream_handle(stream),
+                                                   ctypes.byref(out)))
+    return int(out.value)
 
 
 class Server:

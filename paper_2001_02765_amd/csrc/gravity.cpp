@@ -1525,6 +1525,34 @@ gravity_status_t gravity_solve_batch_persistent(int32_t n, const gravity_plan_t 
     return solve_batch(n, plans, sigma, dsx, dsy, fx, fy, nullptr, workspace, stream, true);
 }
 
+gravity_status_t gravity_batch_persistent_abandoned(int32_t n, const gravity_plan_t *plans, const void *workspace,
+                                                   void *stream, uint32_t *abandoned) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && (!plans || !workspace)) || !abandoned) fail(GRAVITY_EINVAL, "bad arguments");
+        size_t off = 0;
+        bool has[2] = {false, false};
+        for (int i = 0; i < n; ++i) {
+            if (!plans[i]) fail(GRAVITY_EINVAL, "NULL plan");
+            off += align256(plans[i]->ws_bytes);
+            if (persistent_ok(*plans[i])) has[plans[i]->prec] = true;
+        }
+        // the tables sit after the solves' workspaces, one per precision
+        // present, in the order the launches took them (FP32 first)
+        const char *table = (const char *)workspace + off;
+        uint32_t tot = 0;
+        hipStream_t s = (hipStream_t)stream;
+        for (int prec = 0; prec < 2; ++prec) {
+            if (!has[prec]) continue;
+            BatchCtl ctl{};
+            hip_check(hipMemcpyAsync(&ctl, table, sizeof(ctl), hipMemcpyDeviceToHost, s), "control block copy");
+            hip_check(hipStreamSynchronize(s), "control block copy");
+            tot += ctl.timeouts;
+            table += batch_table_bytes(n);
+        }
+        *abandoned = tot;
+    });
+}
+
 gravity_status_t gravity_solve_batch_xyz(int32_t n, const gravity_plan_t *plans, const void *const *sigma,
                                          const void *const *dsx, const void *const *dsy, void *const *fx,
                                          void *const *fy, void *const *fz, void *workspace, void *stream) {

@@ -56,6 +56,11 @@ def test_null_arguments(gl):
     assert gl._lib.gravity_plan_workspace_bytes(None, ctypes.byref(b)) == gl.EINVAL
     assert gl._lib.gravity_plan(None, None) == gl.EINVAL
     assert gl._lib.gravity_batch_workspace_bytes(-1, None, ctypes.byref(b)) == gl.EINVAL
+    u = ctypes.c_uint32(7)
+    assert gl._lib.gravity_batch_persistent_abandoned(0, None, None, None, None) == gl.EINVAL
+    assert gl._lib.gravity_batch_persistent_abandoned(1, None, None, None, ctypes.byref(u)) == gl.EINVAL
+    assert gl._lib.gravity_batch_persistent_abandoned(0, None, None, None, ctypes.byref(u)) == gl.OK
+    assert u.value == 0
     gl._lib.gravity_plan_destroy(None)
 
 

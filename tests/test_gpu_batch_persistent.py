@@ -45,6 +45,8 @@ def _run(gl, plans, ins, persistent, reps=1):
     for _ in range(reps):
         gl.solve_batch(plans, [i[0] for i in ins], [i[1] for i in ins], [i[2] for i in ins],
                        [o[0] for o in outs], [o[1] for o in outs], ws, persistent=persistent)
+        if persistent:  # no unit gave up waiting
+            assert gl.batch_persistent_abandoned(plans, ws) == 0
     torch.cuda.synchronize()
     return outs
 
