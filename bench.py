@@ -9,7 +9,9 @@ latency, the per-stage roofline of the dominant kernel, the whole-solve
 roofline under the compulsory and two-pass byte models, the spread over the
 disks of seeds 0-4, the 2048^2-cell reading of the headline size, the exact
 and nested-correction AMR workloads, the off-plane, batched and served
-workloads (each beside the plain FP64 path), the same convolution through
+workloads (each beside the plain FP64 path), the headline solve's rate
+with several independent solves in flight (batched calls, several streams),
+the same convolution through
 the vendor FFT library (torch.fft, a timing comparator outside the product
 path), the achieved error of every result against the FP64 oracle (relative
 L2 and max|dF|/max|F| on seeded target samples) and the CPU oracle's rate on
@@ -659,6 +661,46 @@ def cpu_baseline_amr(threads, budget_s):
                       "each summed over all %d leaves, %.1f s" % (k, per, len(levels), len(idx), el)}
 
 
+def throughput_leg(gl, torch, n, fields, reps):
+    """Independent solves of the headline disk in flight together: 8 solves
+    per gravity_solve_batch call (one launch per kernel over the 8), and
+    solves spread round-robin over 2 and 3 streams (each with its own
+    workspace and outputs).  The headline value times one solve at a time
+    on one stream; these are the rates a stream of independent solves
+    reaches when the kernels of neighbouring solves overlap."""
+    s, dx, dy, h = fields
+    out = {"workload": "uniform %dx%d cells, zero-padded %d^2 FFT, independent solves in flight together"
+                       % (n, n, 2 * n)}
+    for name, prec, dt in (("f32", gl.F32, torch.float32), ("f64", gl.F64, torch.float64)):
+        plan = gl.Plan(n, prec, h0=h)
+        t = [torch.from_numpy(a.ravel()).to("cuda", dt) for a in (s, dx, dy)]
+        r = {}
+        nb = 8
+        outs = [(torch.empty(n * n, dtype=dt, device="cuda"), torch.empty(n * n, dtype=dt, device="cuda"))
+                for _ in range(nb)]
+        ws = torch.empty(gl.batch_workspace_bytes([plan] * nb), dtype=torch.uint8, device="cuda")
+        ms = _timeit(torch, lambda: gl.solve_batch([plan] * nb, [t[0]] * nb, [t[1]] * nb, [t[2]] * nb,
+                                                    [o[0] for o in outs], [o[1] for o in outs], ws), reps)
+        r["batch8"] = {"ms_per_solve": ms / nb, "forces_per_s": nb * n * n / (ms * 1e-3)}
+        for ns in (2, 3):
+            streams = [torch.cuda.Stream() for _ in range(ns)]
+            wss = [plan.workspace() for _ in range(ns)]
+            k_per = 16
+
+            def run():
+                for k in range(ns * k_per):
+                    i = k % ns
+                    plan.solve(*t, fx=outs[i][0], fy=outs[i][1], workspace=wss[i], stream=streams[i])
+            ms = _timeit(torch, run, max(10, reps))
+            r["streams%d" % ns] = {"ms_per_solve": ms / (ns * k_per),
+                                   "forces_per_s": ns * k_per * n * n / (ms * 1e-3)}
+            del wss
+        out[name] = r
+        del outs, ws
+    torch.cuda.synchronize()
+    return out
+
+
 def library_fft_leg(gl, torch, n, reps, ours):
     """Timing comparator outside the product path: the same zero-padded
     convolution written with the vendor FFT library through torch.fft
@@ -849,6 +891,7 @@ def main():
     if not args.no_extra:
         legs = (("seed_spread", lambda: seed_spread(gl, torch, n, max(20, args.steps // 2), args.warmup,
                                                     r32["value"])),
+                ("throughput", lambda: throughput_leg(gl, torch, n, fields, max(10, args.steps // 10))),
                 ("library_fft", lambda: library_fft_leg(gl, torch, n, max(20, args.steps // 4),
                                                         {"f32": r32["ms_per_step"], "f64": r64["ms_per_step"]})),
                 ("n2048", lambda: n2048_leg(gl, torch, max(10, args.steps // 4), 5)),
