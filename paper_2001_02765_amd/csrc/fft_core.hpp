@@ -330,6 +330,7 @@ template <typename T, int L, int NT> struct TwReg {
 // elements with constant offsets (an XOR swizzle spreads the banks better
 // but costs address arithmetic per element, which measured slower).
 struct LdsSoA {
+    static constexpr bool kSoA = true;
     static constexpr int BLK = 32;
     int reg;
     __device__ __forceinline__ int at(int i, int x) const { return i * reg + x + (x >> 5); }
@@ -338,6 +339,7 @@ struct LdsSoA {
     template <int L> static constexpr int region() { return L + (L >> 5) + 1; }
 };
 struct LdsAoS {
+    static constexpr bool kSoA = false;
     static constexpr int BLK = 8;
     int stride, lane;
     __device__ __forceinline__ int at(int, int x) const { return (x + (x >> 3)) * stride + lane; }
@@ -366,6 +368,9 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds0, const MAP
     int t = t_in;
     asm volatile("" : "+v"(t));
     C<T> *lds = (PPO > 0 && (P & 1)) ? lds0 + PPO : lds0;
+    // FP64 column exchanges: real and imaginary parts in separate planes of
+    // the region (8-byte accesses, as in FP32, instead of 16-byte ones)
+    constexpr bool PLANAR = sizeof(T) == 8 && MAP::kSoA;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + NT * b;
@@ -393,6 +398,23 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds0, const MAP
             if constexpr (LAST) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) reg[i][b + r * B] = v[r];
+            } else if constexpr (PLANAR) {
+                const int base = (j / NS) * NS * R + k;
+                T *pr = reinterpret_cast<T *>(lds) + map.ioff(i);
+                if constexpr (NS * R >= MAP::BLK) {
+                    pr += map.at(i, base);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        pr[map.off(r * NS)] = v[r].x;
+                        pr[map.reg + map.off(r * NS)] = v[r].y;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        pr[map.at(i, base + r * NS)] = v[r].x;
+                        pr[map.reg + map.at(i, base + r * NS)] = v[r].y;
+                    }
+                }
             } else {
                 const int base = (j / NS) * NS * R + k;
                 if constexpr (NS * R >= MAP::BLK) {
@@ -409,7 +431,15 @@ __device__ __forceinline__ void mpass(C<T> (*reg)[L / NT], C<T> *lds0, const MAP
     }
     if constexpr (!LAST) {
         block_sync();
-        {
+        if constexpr (PLANAR) {
+            const T *pr = reinterpret_cast<const T *>(lds) + map.at(0, t);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    reg[i][e] = mk<T>(pr[2 * map.ioff(i) + map.off(NT * e)],
+                                      pr[2 * map.ioff(i) + map.reg + map.off(NT * e)]);
+        } else {
             // NT and BLK are powers of two: t mod BLK + (NT e) mod BLK < BLK
             const C<T> *p = lds + map.at(0, t);
 #pragma unroll
