@@ -557,6 +557,16 @@ def test_invalid_requests(gl):
         p.solve(s.double(), s, s)
 
 
+def test_empty_batch_is_a_no_op(gl):
+    """A batch of no solves queues nothing, in the grouped and the
+    persistent form (its workspace is the persistent launch's table room)."""
+    ws = torch.empty(max(1, gl.batch_workspace_bytes([])), dtype=torch.uint8, device="cuda")
+    gl.solve_batch([], [], None, None, [], [], ws)
+    gl.solve_batch([], [], None, None, [], [], ws, persistent=True)
+    assert gl.batch_persistent_abandoned([], ws) == 0
+    torch.cuda.synchronize()
+
+
 def test_server_results_same_alone_and_in_mix(gl):
     """Continuous batching: a mixed stream (sizes, precisions, uniform and AMR)
     submitted to a server under a tight HBM budget gives every request the
